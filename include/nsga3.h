@@ -1,0 +1,148 @@
+/*
+ * nsga3.h -- C-ABI of libnsga3.so: NSGA-III environmental selection on an
+ * AMD Instinct MI355X (gfx950), one GPU.
+ *
+ * The calls follow the paper's statement of selection (arXiv 2504.06067):
+ * Algorithm 1 (input: merged population R_t = P_t u O_t of size 2N and the
+ * reference set Z; output: the next population of size N) and its
+ * tensorized restatement Algorithm 2 (normalize, associate, niche counts,
+ * niche fill of the last front). nsga3_select runs the four stages in order;
+ * the stage calls exist so that each can be driven and checked on its own.
+ *
+ * Conventions for every call:
+ *  - Pointers are DEVICE memory unless marked [host]. The caller owns all
+ *    memory; the library never allocates, frees or synchronizes inside a
+ *    compute call. Work is enqueued on `stream` (a hipStream_t; NULL means
+ *    the null stream) and the call returns at once. Pointers must stay valid
+ *    until that work completes.
+ *  - Arguments are validated on the host before anything is enqueued. On
+ *    NSGA3_EINVAL / NSGA3_EWORKSPACE nothing is enqueued.
+ *  - Objectives are minimized. F is row-major [M][m] float32, m in [2, 16],
+ *    2 <= M <= 2^20. Z is row-major [H][m] float32 with finite, non-negative,
+ *    non-zero rows (e.g. a Das-Dennis lattice); the library scales each row
+ *    to unit length itself.
+ *  - Problems that only the data reveals (non-finite objectives, an invalid
+ *    reference row, a broken internal invariant) set a status word inside the
+ *    workspace; read it with nsga3_read_status after the work completes.
+ *    Outputs are then unspecified (but every write stays in bounds).
+ *  - `ws` is a device buffer of at least nsga3_workspace_bytes(M, m, H, N)
+ *    bytes, 256-byte aligned. Calls that overlap in time need distinct
+ *    workspaces. The status word reflects the most recent call on `ws`.
+ *  - Ranks are 0-based (the paper's first front F_1 is rank 0). Points in
+ *    fronts after the last selected front l are NSGA3_UNRANKED.
+ *  - front_info is int32[4] = {l, |S|, K, fronts ranked}: S is the union of
+ *    fronts 0..l-1 (all selected) and K = N - |S| >= 1 points are taken from
+ *    front l by niching.
+ *  - Random tie-breaks (Algorithm 1: the random choice among least-crowded
+ *    reference points and of a member) are deterministic functions of `seed`:
+ *    key(seed, tag, j, L) = sm64(seed ^ sm64((tag << 62) | (L << 32) | j))
+ *    with sm64 the SplitMix64 output function. Among least-crowded
+ *    references at niche count L the least tag-1 key goes first; a random
+ *    member pick of reference j at niche count L takes the
+ *    (key(seed, 2, j, L) mod r)-th of its r remaining candidates in
+ *    ascending index order. The result equals the one-pick-per-iteration loop
+ *    of Algorithm 1 under these keys, bit for bit.
+ */
+#ifndef NSGA3_H
+#define NSGA3_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    NSGA3_OK = 0,
+    NSGA3_EINVAL = -1,      /* bad argument (nothing enqueued) or invalid reference row (status) */
+    NSGA3_EWORKSPACE = -2,  /* ws_bytes below nsga3_workspace_bytes (nothing enqueued) */
+    NSGA3_EHIP = -3,        /* a HIP runtime call failed */
+    NSGA3_ENONFINITE = -4,  /* status: an objective is NaN or infinite */
+    NSGA3_EINTERNAL = -5    /* status: an internal invariant failed */
+};
+
+#define NSGA3_UNRANKED 0x7fffffff
+#define NSGA3_MAX_OBJECTIVES 16
+#define NSGA3_MAX_POINTS (1 << 20)
+
+/* Workspace size in bytes for one selection of M merged points, m objectives,
+ * H references, N survivors. Pure host function. The dominant term is the
+ * bit-packed dominance matrix, ceil(M/64)^2 * 512 bytes. Returns 0 for
+ * arguments that every compute call would reject. */
+size_t nsga3_workspace_bytes(int32_t M, int32_t m, int32_t H, int32_t N);
+
+/* Non-dominated sorting of the merged population (Sec. II-C; Algorithm 1,
+ * "Non-dominated-sort"), then the front fill: l is the first front at which
+ * the cumulative size reaches n_stop (n_stop <= 0 or > M means M).
+ * Builds the bit-packed dominance matrix (bit i of row j: point i dominates
+ * point j), peels fronts with popcounts over it, and stops at front l.
+ *   F          [M][m] float32 objectives (read)
+ *   rank       int32[M] (write): 0-based front index, NSGA3_UNRANKED after l
+ *   front_info int32[4] (write): {l, |S|, K, l + 1}                           */
+int nsga3_nd_sort(const float *F, int32_t M, int32_t m, int32_t n_stop,
+                  int32_t *rank, int32_t *front_info,
+                  void *ws, size_t ws_bytes, void *stream);
+
+/* Normalization of S_t = {x : rank[x] <= l} (Algorithm 1 "associate ...
+ * using normalized objectives"; Algorithm 2 "Normalize"), the procedure of
+ * Deb & Jain 2014 cited by the paper: ideal point z (least value per
+ * objective over S_t); extreme point e_k = argmin over S_t of
+ * max(f'_k, 1e6 * max_{j != k} f'_j) with f' = f - z (least index on ties);
+ * intercepts a from the hyperplane through the extreme points, solved in
+ * FP64 by Gaussian elimination with partial pivoting. If the system is
+ * degenerate (pivot below 1e-10 of its column's largest entry, a
+ * non-positive or non-finite intercept, or a_k below 1e-6 of the largest f'_k
+ * over S_t) every a_k is the largest f'_k over S_t (1 where that is 0).
+ * Then Fn = (f - z) / a for rows in S_t.
+ *   F, rank, front_info   as produced by nsga3_nd_sort (read)
+ *   Fn          [M][m] float32 (write; rows outside S_t untouched)
+ *   ideal       float32[m], intercept float64[m], extreme int32[m],
+ *   degenerate  int32[1] (0 or 1)                                    (write)  */
+int nsga3_normalize(const float *F, const int32_t *rank, const int32_t *front_info,
+                    int32_t M, int32_t m, float *Fn, float *ideal, double *intercept,
+                    int32_t *extreme, int32_t *degenerate,
+                    void *ws, size_t ws_bytes, void *stream);
+
+/* Association (Sec. II-C; Eq. 1 and Algorithm 2, argmin/min over the
+ * references): every x in S_t gets the reference j whose direction
+ * w_j / ||w_j|| has the least perpendicular distance
+ * d = || f - (f . w) w || to Fn[x] (least j on ties).
+ *   Fn          [M][m] float32 normalized objectives (read; rows of S_t)
+ *   Z           [H][m] float32 reference points (read)
+ *   pi          int32[M] (write): reference index; -1 outside S_t
+ *   dist        float32[M] (write): perpendicular distance; -1 outside S_t */
+int nsga3_associate(const float *Fn, const int32_t *rank, const int32_t *front_info,
+                    int32_t M, int32_t m, const float *Z, int32_t H,
+                    int32_t *pi, float *dist, void *ws, size_t ws_bytes, void *stream);
+
+/* Niching (Algorithm 1 while-loop; Algorithm 2 nearest and random
+ * selection, cache tensor and truncation): niche counts rho over S, then K
+ * picks from front l, least-crowded reference first; a reference at niche
+ * count 0 takes its nearest candidate (least dist, then least index),
+ * otherwise a keyed random one. Output: the N selected indices, ascending.
+ *   rank, front_info, pi, dist  (read), selected int32[N] (write)            */
+int nsga3_niche(const int32_t *rank, const int32_t *front_info, const int32_t *pi,
+                const float *dist, int32_t M, int32_t H, int32_t N, uint64_t seed,
+                int32_t *selected, void *ws, size_t ws_bytes, void *stream);
+
+/* The whole selection: nd_sort(n_stop = N) -> normalize -> associate ->
+ * niche. rank_out int32[M], pi_out int32[M] and dist_out float32[M] may be
+ * NULL; when given they receive the intermediate results. */
+int nsga3_select(const float *F, int32_t M, int32_t m, const float *Z, int32_t H,
+                 int32_t N, uint64_t seed, int32_t *selected, int32_t *rank_out,
+                 int32_t *pi_out, float *dist_out,
+                 void *ws, size_t ws_bytes, void *stream);
+
+/* Waits for `stream`, then reads the status word of `ws` into *status [host]
+ * (NSGA3_OK, NSGA3_ENONFINITE, NSGA3_EINVAL or NSGA3_EINTERNAL). Returns
+ * NSGA3_OK, or NSGA3_EHIP if the copy or the wait failed. */
+int nsga3_read_status(const void *ws, void *stream, int32_t *status);
+
+/* Library version string [host, static storage]. */
+const char *nsga3_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NSGA3_H */

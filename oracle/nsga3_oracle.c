@@ -115,9 +115,8 @@ int oracle_nd_sort(const float *F, int M, int m, int n_stop,
         full[p] = -1;
         if (n[p] == 0) { cur[ncur++] = p; full[p] = 0; }
     }
-    int k = 0, fronts = 0, cum = 0, l = -1, cum_before_l = 0;
+    int k = 0, cum = 0, l = -1, cum_before_l = 0;
     while (ncur > 0) {
-        fronts = k + 1;
         if (l < 0 && cum + ncur >= N) { l = k; cum_before_l = cum; }
         cum += ncur;
         int nn = 0;
@@ -137,7 +136,7 @@ int oracle_nd_sort(const float *F, int M, int m, int n_stop,
     front_info[0] = l;
     front_info[1] = cum_before_l;
     front_info[2] = N - cum_before_l;
-    front_info[3] = fronts;
+    front_info[3] = l + 1; /* fronts ranked: 0..l (later ones are reported unranked) */
 
     for (int p = 0; p < M; ++p) free(S[p].v);
     free(S); free(n); free(full); free(cur); free(nxt);

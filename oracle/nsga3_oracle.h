@@ -16,7 +16,7 @@
  *   - objectives are minimized; F is row-major [M][m] float32;
  *   - ranks are 0-based; points in fronts after the last selected front carry
  *     ORACLE_UNRANKED;
- *   - front_info = {l, |S|, K, fronts_ranked} with l the 0-based index of the
+ *   - front_info = {l, |S|, K, l + 1} with l the 0-based index of the
  *     last (partially selected) front, S the fully selected fronts, and
  *     K = N - |S| the number of picks made from front l;
  *   - selected[] is the ascending list of the N chosen indices.

@@ -1,0 +1,471 @@
+// Niching (Algorithm 1 niche-selection loop; Algorithm 2 nearest selection,
+// cache tensor Q, random selection loop and truncation).
+//
+// The paper removes the serial loop's cost with a cache tensor and a
+// batched while-loop. Here the loop is replaced by its closed form. In the
+// sequential loop every reference that still has candidates is served once at
+// niche count L, in key order, before any is served at L + 1; references
+// interact only through the shared budget K. With
+//   P(L) = sum_j min(c_j, max(0, L - rho_j))      (picks needed to fill to L)
+// the last complete level is L* = max{L : P(L) <= K}; the r = K - P(L*)
+// references of T = {j : rho_j <= L* < rho_j + c_j} with least
+// key(seed, 1, j, L*) get one more pick. Each reference then makes its own
+// picks at its levels rho_j .. rho_j + t_j - 1: the nearest candidate at
+// level 0, otherwise candidate (key(seed, 2, j, L) mod remaining) in
+// ascending index order. The result equals the one-pick-per-iteration loop.
+//
+// Kernels:
+//   k_niche_init     zero counters and flags
+//   k_niche_count    rho (fronts < l) and c (front l) per reference
+//   k_niche_plan     one workgroup: CSR offsets, L*, radix select of the r
+//                    least keys, per-reference pick counts t_j
+//   k_niche_scatter  members of front l into per-reference segments
+//   k_niche_pick     one wave per reference: sort its segment ascending,
+//                    make its picks with a remaining-set bitmask
+//   k_compact_count / k_compact_write   ascending output of S and the picks
+#include "nsga3_internal.h"
+
+namespace nsga3 {
+
+constexpr int PLAN_THREADS = 1024;
+constexpr int PICK_CAP = 2048;          // segment length kept in LDS by one wave
+constexpr int TILE = 4096;              // compaction tile
+
+__global__ __launch_bounds__(256) void k_niche_init(int H, int M, int *rho, int *cnt, int *fill,
+                                                     int *picked, Ctrl *ctrl, bool reset_status) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t == 0 && reset_status) ctrl->status = 0;
+    if (t < H) {
+        rho[t] = 0;
+        cnt[t] = 0;
+        fill[t] = 0;
+    }
+    if (t < M) picked[t] = 0;
+}
+
+__global__ __launch_bounds__(256) void k_niche_count(const int *__restrict__ rank,
+                                                      const int *__restrict__ front_info,
+                                                      const int *__restrict__ pi, int M, int H,
+                                                      int *rho, int *cnt, Ctrl *ctrl) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= M) return;
+    const int l = front_info[0];
+    const int r = rank[x];
+    if (r < 0 || r > l) return;
+    const int p = pi[x];
+    if (p < 0 || p >= H) {
+        atomicOr(&ctrl->status, ST_INTERNAL);
+        return;
+    }
+    atomicAdd(r < l ? &rho[p] : &cnt[p], 1);
+}
+
+__device__ __forceinline__ long long block_sum_ll(long long v, long long *red) {
+    v = wave_sum(v);
+    const int w = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane_id() == 0) red[w] = v;
+    __syncthreads();
+    long long s = 0;
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) s += red[i];
+    return uniform(s);
+}
+
+__global__ __launch_bounds__(PLAN_THREADS) void k_niche_plan(const int *__restrict__ front_info,
+                                                              const int *__restrict__ rho,
+                                                              const int *__restrict__ cnt, int H,
+                                                              u64 seed, int *off, int *tpick,
+                                                              Ctrl *ctrl) {
+    __shared__ long long red[PLAN_THREADS / 64];
+    __shared__ int part[PLAN_THREADS];
+    __shared__ unsigned hist[256];
+    __shared__ int s_sel[2];
+    const int tid = threadIdx.x;
+    const int wv = uniform((int)(threadIdx.x >> 6));
+    const int lane = lane_id();
+    const int K = uniform(front_info[2]);
+
+    // exclusive scan of c over contiguous per-thread ranges
+    const int per = (H + PLAN_THREADS - 1) / PLAN_THREADS;
+    const int b0 = min(tid * per, H), b1 = min(b0 + per, H);
+    int local = 0;
+    for (int j = b0; j < b1; ++j) local += cnt[j];
+    part[tid] = local;
+    __syncthreads();
+    if (wv == 0) {
+        // wave 0 scans the 1024 partial sums, 16 per lane
+        int s = 0;
+        for (int q = 0; q < 16; ++q) s += part[lane * 16 + q];
+        const int incl = wave_incl_scan(s);
+        int run = incl - s;
+        for (int q = 0; q < 16; ++q) {
+            const int v = part[lane * 16 + q];
+            part[lane * 16 + q] = run;
+            run += v;
+        }
+    }
+    __syncthreads();
+    int run = part[tid];
+    for (int j = b0; j < b1; ++j) {
+        off[j] = run;
+        run += cnt[j];
+    }
+    if (b1 == H && b0 < b1) off[H] = run;
+    long long total = 0;
+    for (int j = tid; j < H; j += PLAN_THREADS) total += cnt[j];
+    total = block_sum_ll(total, red);
+
+    if (K >= total) {
+        // the whole last front is taken
+        for (int j = tid; j < H; j += PLAN_THREADS) tpick[j] = cnt[j];
+        if (wv == 0) {
+            ctrl->all_pick = 1;
+            ctrl->lstar = -1;
+            ctrl->rpick = 0;
+            ctrl->fl_total = (int)total;
+            if (K > total) atomicOr(&ctrl->status, ST_INTERNAL);
+        }
+        return;
+    }
+    // L* = max{L : P(L) <= K}; P(0) = 0 <= K < total = P(hi)
+    long long hi_l = 0;
+    for (int j = tid; j < H; j += PLAN_THREADS)
+        if (cnt[j] > 0) hi_l = max(hi_l, (long long)rho[j] + cnt[j]);
+    {
+        // block-wide maximum
+        long long v = hi_l;
+        for (int o = 32; o > 0; o >>= 1) v = max(v, (long long)__shfl_xor(v, o, 64));
+        __syncthreads();
+        if (lane_id() == 0) red[tid >> 6] = v;
+        __syncthreads();
+        hi_l = 0;
+        for (int i = 0; i < PLAN_THREADS / 64; ++i) hi_l = max(hi_l, red[i]);
+        hi_l = uniform(hi_l);
+    }
+    long long lo = 0, hi = hi_l;
+    while (hi - lo > 1) {
+        const long long mid = (lo + hi) >> 1;
+        long long p = 0;
+        for (int j = tid; j < H; j += PLAN_THREADS)
+            p += min((long long)cnt[j], max(0ll, mid - rho[j]));
+        p = block_sum_ll(p, red);
+        if (p <= K) lo = mid; else hi = mid;
+    }
+    const int Ls = (int)lo;
+    long long pl = 0;
+    for (int j = tid; j < H; j += PLAN_THREADS) pl += min((long long)cnt[j], max(0ll, (long long)Ls - rho[j]));
+    pl = block_sum_ll(pl, red);
+    const int r = (int)(K - pl);
+
+    // radix select (8 bits per pass, most significant first) of the r-th least
+    // key among T; keys of distinct references differ (sm64 is a bijection)
+    u64 prefix = 0, pmask = 0;
+    int need = r;
+    if (r > 0) {
+        for (int pass = 0; pass < 8; ++pass) {
+            const int shift = 56 - 8 * pass;
+            for (int q = tid; q < 256; q += PLAN_THREADS) hist[q] = 0;
+            __syncthreads();
+            for (int j = tid; j < H; j += PLAN_THREADS) {
+                if (cnt[j] > 0 && rho[j] <= Ls && Ls < rho[j] + cnt[j]) {
+                    const u64 kj = tie_key(seed, 1u, (unsigned)j, (unsigned)Ls);
+                    if ((kj & pmask) == prefix) atomicAdd(&hist[(kj >> shift) & 255u], 1u);
+                }
+            }
+            __syncthreads();
+            if (wv == 0) {
+                // lane L holds bins 4L..4L+3; find the bin where the running
+                // count first reaches `need`
+                int h[4], sum = 0;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) { h[q] = (int)hist[4 * lane + q]; sum += h[q]; }
+                const int incl = wave_incl_scan(sum);
+                const u64 reach = ballot(incl >= need);
+                const int L = reach ? __ffsll((long long)reach) - 1 : 63;
+                int acc = uniform(__builtin_amdgcn_readlane(incl - sum, L));
+                int d = 4 * L + 3;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int hq = uniform(__builtin_amdgcn_readlane(h[q], L));
+                    if (acc + hq >= need) { d = 4 * L + q; break; }
+                    acc += hq;
+                }
+                s_sel[0] = d;
+                s_sel[1] = need - acc;
+            }
+            __syncthreads();
+            prefix |= (u64)uniform(s_sel[0]) << shift;
+            pmask |= 255ull << shift;
+            need = uniform(s_sel[1]);
+            __syncthreads();
+        }
+    }
+    for (int j = tid; j < H; j += PLAN_THREADS) {
+        int t = (int)min((long long)cnt[j], max(0ll, (long long)Ls - rho[j]));
+        if (r > 0 && cnt[j] > 0 && rho[j] <= Ls && Ls < rho[j] + cnt[j] &&
+            tie_key(seed, 1u, (unsigned)j, (unsigned)Ls) <= prefix)
+            t += 1;
+        tpick[j] = t;
+    }
+    if (wv == 0) {
+        ctrl->all_pick = 0;
+        ctrl->lstar = Ls;
+        ctrl->rpick = r;
+        ctrl->fl_total = (int)total;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_niche_scatter(const int *__restrict__ rank,
+                                                        const int *__restrict__ front_info,
+                                                        const int *__restrict__ pi, int M, int H,
+                                                        const int *__restrict__ off, int *fill,
+                                                        int *members) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= M) return;
+    if (rank[x] != front_info[0]) return;
+    const int p = pi[x];
+    if (p < 0 || p >= H) return;
+    const int slot = atomicAdd(&fill[p], 1);
+    members[off[p] + slot] = x;
+}
+
+// Makes every lane's earlier LDS and global writes visible to the other lanes
+// of the wave before any later read.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// Ascending bitonic sort of buf[0..n) by one wave; positions >= n act as +inf
+// (the "flip then half-clean" form needs no explicit padding).
+__device__ void wave_sort(int *buf, int n) {
+    const int lane = lane_id();
+    int np = 1;
+    while (np < n) np <<= 1;
+    for (int size = 2; size <= np; size <<= 1) {
+        // flip: compare i with the mirror partner in its block of `size`
+        for (int i = lane; i < np / 2; i += 64) {
+            const int blk = i / (size / 2);
+            const int pos = i % (size / 2);
+            const int a = blk * size + pos;
+            const int b = blk * size + size - 1 - pos;
+            if (b < n) {
+                const int va = buf[a], vb = buf[b];
+                if (va > vb) { buf[a] = vb; buf[b] = va; }
+            }
+        }
+        wave_sync();
+        for (int half = size / 4; half >= 1; half >>= 1) {
+            for (int i = lane; i < np / 2; i += 64) {
+                const int blk = i / half;
+                const int pos = i % half;
+                const int a = blk * 2 * half + pos;
+                const int b = a + half;
+                if (b < n) {
+                    const int va = buf[a], vb = buf[b];
+                    if (va > vb) { buf[a] = vb; buf[b] = va; }
+                }
+            }
+            wave_sync();
+        }
+    }
+}
+
+// Position of the k-th (0-based) set bit of w.
+__device__ __forceinline__ int select_bit(u64 w, int k) {
+    int pos = 0;
+#pragma unroll
+    for (int width = 32; width >= 1; width >>= 1) {
+        const u64 lowmask = (width == 64) ? ~0ull : ((1ull << width) - 1);
+        const int c = __popcll(w & lowmask);
+        if (k >= c) { k -= c; w >>= width; pos += width; }
+    }
+    return pos;
+}
+
+// One wave per reference (4 per workgroup). Segments up to PICK_CAP are
+// sorted and tracked in LDS; longer ones in place in global memory.
+__global__ __launch_bounds__(256) void k_niche_pick(const int *__restrict__ rho,
+                                                     const int *__restrict__ cnt,
+                                                     const int *__restrict__ off,
+                                                     const int *__restrict__ tpick,
+                                                     const float *__restrict__ dist, int H,
+                                                     u64 seed, int *members, u64 *remain_g,
+                                                     int *picked) {
+    __shared__ int s_buf[4][PICK_CAP];
+    __shared__ u64 s_rem[4][PICK_CAP / 64];
+    const int wv = threadIdx.x >> 6;
+    const int lane = lane_id();
+    const int j = blockIdx.x * 4 + wv;
+    if (j >= H) return;
+    const int t = tpick[j];
+    if (t <= 0) return;
+    const int c = cnt[j];
+    int *seg = members + off[j];
+    if (t >= c) {
+        for (int i = lane; i < c; i += 64) picked[seg[i]] = 1;
+        return;
+    }
+    const int rj = rho[j];
+    if (t == 1 && rj == 0) {
+        // a single pick at niche count 0: the nearest candidate
+        u64 best = ~0ull;
+        for (int i = lane; i < c; i += 64) {
+            const int x = seg[i];
+            const u64 k = ((u64)__float_as_uint(dist[x]) << 32) | (unsigned)x;
+            best = k < best ? k : best;
+        }
+        best = wave_min_u64(best);
+        if (lane == 0) picked[(int)(unsigned)(best & 0xffffffffull)] = 1;
+        return;
+    }
+    int *buf;
+    u64 *rem;
+    if (c <= PICK_CAP) {
+        buf = s_buf[wv];
+        rem = s_rem[wv];
+        for (int i = lane; i < c; i += 64) buf[i] = seg[i];
+        wave_sync();
+    } else {
+        buf = seg;
+        rem = remain_g + (off[j] >> 6) + j;
+    }
+    wave_sort(buf, c);
+    const int nw = (c + 63) / 64;
+    for (int w = lane; w < nw; w += 64) {
+        const int v = c - w * 64;
+        rem[w] = v >= 64 ? ~0ull : ((1ull << v) - 1);
+    }
+    // lane L owns words [L*s, (L+1)*s) and keeps their population count
+    const int s = (nw + 63) / 64;
+    int own = 0;
+    for (int w = lane * s; w < min(nw, (lane + 1) * s); ++w) own += __popcll(rem[w]);
+    wave_sync();
+    for (int lev = rj; lev < rj + t; ++lev) {
+        const int remaining = c - (lev - rj);
+        int pos;
+        if (lev == 0) {
+            // first pick of a reference at niche count 0: the nearest candidate
+            u64 best = ~0ull;
+            for (int i = lane; i < c; i += 64) {
+                const int x = buf[i];
+                const u64 k = ((u64)__float_as_uint(dist[x]) << 32) | (unsigned)i;
+                best = k < best ? k : best;
+            }
+            best = wave_min_u64(best);
+            pos = (int)(unsigned)(best & 0xffffffffull);
+        } else {
+            const int kk = (int)(tie_key(seed, 2u, (unsigned)j, (unsigned)lev) % (u64)remaining);
+            const int incl = wave_incl_scan(own);
+            const int excl = incl - own;
+            const u64 owner = ballot(excl <= kk && kk < incl);
+            if (owner == 0) break;  // unreachable while the counts are consistent
+            const int L = __ffsll((long long)owner) - 1;
+            int found = 0;
+            if (lane == L) {
+                int k2 = kk - excl;
+                for (int w = lane * s; w < min(nw, (lane + 1) * s); ++w) {
+                    const int pc = __popcll(rem[w]);
+                    if (k2 < pc) { found = w * 64 + select_bit(rem[w], k2); break; }
+                    k2 -= pc;
+                }
+            }
+            pos = __shfl(found, L, 64);
+        }
+        if (pos < 0 || pos >= c) break;
+        // remove position pos
+        if (lane == 0) rem[pos >> 6] &= ~(1ull << (pos & 63));
+        if (lane == (pos >> 6) / s) own -= 1;
+        if (lane == 0) picked[buf[pos]] = 1;
+        wave_sync();
+    }
+}
+
+// Compaction of {x : rank[x] < l or picked[x]} in ascending order.
+__global__ __launch_bounds__(256) void k_compact_count(const int *__restrict__ rank,
+                                                        const int *__restrict__ front_info,
+                                                        const int *__restrict__ picked, int M,
+                                                        int *tiles) {
+    __shared__ long long red[4];
+    const int l = front_info[0];
+    const int base = blockIdx.x * TILE;
+    long long c = 0;
+    for (int i = threadIdx.x; i < TILE; i += 256) {
+        const int x = base + i;
+        if (x < M) {
+            const int r = rank[x];
+            c += (r >= 0 && r < l) || picked[x];
+        }
+    }
+    c = block_sum_ll(c, red);
+    if (threadIdx.x == 0) tiles[blockIdx.x] = (int)c;
+}
+
+__global__ __launch_bounds__(256) void k_compact_write(const int *__restrict__ rank,
+                                                        const int *__restrict__ front_info,
+                                                        const int *__restrict__ picked,
+                                                        const int *__restrict__ tiles, int ntiles,
+                                                        int M, int N, int *selected, Ctrl *ctrl) {
+    __shared__ long long red[4];
+    __shared__ int wsum[4];
+    const int l = front_info[0];
+    long long before = 0;
+    for (int b = threadIdx.x; b < (int)blockIdx.x; b += 256) before += tiles[b];
+    before = block_sum_ll(before, red);
+    // thread t owns TILE/256 = 16 consecutive points
+    constexpr int PER = TILE / 256;
+    const int x0 = blockIdx.x * TILE + threadIdx.x * PER;
+    int flags = 0, n = 0;
+    for (int q = 0; q < PER; ++q) {
+        const int x = x0 + q;
+        int f = 0;
+        if (x < M) {
+            const int r = rank[x];
+            f = (r >= 0 && r < l) || picked[x];
+        }
+        flags |= f << q;
+        n += f;
+    }
+    const int incl = wave_incl_scan(n);
+    const int wv = threadIdx.x >> 6;
+    if (lane_id() == 63) wsum[wv] = incl;
+    __syncthreads();
+    int woff = 0;
+    for (int i = 0; i < wv; ++i) woff += wsum[i];
+    int pos = (int)before + woff + incl - n;
+    for (int q = 0; q < PER; ++q) {
+        if ((flags >> q) & 1) {
+            if (pos < N) selected[pos] = x0 + q;
+            ++pos;
+        }
+    }
+    if (blockIdx.x == (unsigned)(ntiles - 1) && threadIdx.x == 255) {
+        if (pos != N) atomicOr(&ctrl->status, ST_INTERNAL);
+    }
+}
+
+hipError_t launch_niche(const Layout &L, const Ptrs &P, const int *rank, const int *front_info,
+                        const int *pi, const float *dist, u64 seed, int *selected,
+                        bool reset_status, hipStream_t s) {
+    const int M = L.M, H = L.H, N = L.N;
+    const int nt = M > H ? M : H;
+    hipLaunchKernelGGL(k_niche_init, dim3((nt + 255) / 256), dim3(256), 0, s, H, M, P.rho, P.cnt,
+                       P.fill, P.picked, P.ctrl, reset_status);
+    hipLaunchKernelGGL(k_niche_count, dim3((M + 255) / 256), dim3(256), 0, s, rank, front_info,
+                       pi, M, H, P.rho, P.cnt, P.ctrl);
+    hipLaunchKernelGGL(k_niche_plan, dim3(1), dim3(PLAN_THREADS), 0, s, front_info, P.rho, P.cnt,
+                       H, seed, P.off, P.tpick, P.ctrl);
+    hipLaunchKernelGGL(k_niche_scatter, dim3((M + 255) / 256), dim3(256), 0, s, rank, front_info,
+                       pi, M, H, P.off, P.fill, P.members);
+    hipLaunchKernelGGL(k_niche_pick, dim3((H + 3) / 4), dim3(256), 0, s, P.rho, P.cnt, P.off,
+                       P.tpick, dist, H, seed, P.members, P.remain, P.picked);
+    const int ntiles = (M + TILE - 1) / TILE;
+    hipLaunchKernelGGL(k_compact_count, dim3(ntiles), dim3(256), 0, s, rank, front_info, P.picked,
+                       M, P.tiles);
+    hipLaunchKernelGGL(k_compact_write, dim3(ntiles), dim3(256), 0, s, rank, front_info, P.picked,
+                       P.tiles, ntiles, M, N, selected, P.ctrl);
+    return hipGetLastError();
+}
+
+}  // namespace nsga3

@@ -1,0 +1,196 @@
+"""Python binding of libnsga3.so (argument marshalling only).
+
+Every function takes and returns torch tensors on the GPU, checks dtypes and
+shapes, allocates outputs and the workspace with torch, and calls the C-ABI
+declared in ``include/nsga3.h`` on the current HIP stream. All arithmetic
+runs in the library's HIP kernels; there is no fallback: if the library is
+missing the first call raises.
+"""
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libnsga3.so")
+
+OK, EINVAL, EWORKSPACE, EHIP, ENONFINITE, EINTERNAL = 0, -1, -2, -3, -4, -5
+UNRANKED = 0x7FFFFFFF
+_NAMES = {0: "OK", -1: "EINVAL", -2: "EWORKSPACE", -3: "EHIP", -4: "ENONFINITE", -5: "EINTERNAL"}
+
+_lib = None
+
+
+class Nsga3Error(RuntimeError):
+    def __init__(self, code, what):
+        super().__init__(f"{what}: {_NAMES.get(code, code)}")
+        self.code = code
+
+
+def lib():
+    """The loaded library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"libnsga3.so not built at {LIB_PATH}; run __graft_entry__.build()")
+    L = ctypes.CDLL(LIB_PATH)
+    P, i32, u64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint64, ctypes.c_size_t
+    L.nsga3_workspace_bytes.argtypes = [i32, i32, i32, i32]
+    L.nsga3_workspace_bytes.restype = sz
+    L.nsga3_nd_sort.argtypes = [P, i32, i32, i32, P, P, P, sz, P]
+    L.nsga3_normalize.argtypes = [P, P, P, i32, i32, P, P, P, P, P, P, sz, P]
+    L.nsga3_associate.argtypes = [P, P, P, i32, i32, P, i32, P, P, P, sz, P]
+    L.nsga3_niche.argtypes = [P, P, P, P, i32, i32, i32, u64, P, P, sz, P]
+    L.nsga3_select.argtypes = [P, i32, i32, P, i32, i32, u64, P, P, P, P, P, sz, P]
+    L.nsga3_read_status.argtypes = [P, P, P]
+    L.nsga3_version.restype = ctypes.c_char_p
+    for f in ("nsga3_nd_sort", "nsga3_normalize", "nsga3_associate", "nsga3_niche",
+              "nsga3_select", "nsga3_read_status"):
+        getattr(L, f).restype = i32
+    _lib = L
+    return L
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _stream(device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _check(rc, what):
+    if rc != OK:
+        raise Nsga3Error(rc, what)
+
+
+def workspace_bytes(M, m, H, N):
+    return int(lib().nsga3_workspace_bytes(int(M), int(m), int(H), int(N)))
+
+
+class Workspace:
+    """A reusable device workspace, grown on demand (allocation happens here,
+    never inside a library call)."""
+
+    def __init__(self, device="cuda"):
+        self.device = torch.device(device)
+        self.buf = None
+
+    def get(self, nbytes):
+        if self.buf is None or self.buf.numel() < nbytes:
+            self.buf = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=self.device)
+        return self.buf
+
+    def status(self):
+        st = ctypes.c_int32(0)
+        _check(lib().nsga3_read_status(_ptr(self.buf), _stream(self.device), ctypes.byref(st)),
+               "nsga3_read_status")
+        return st.value
+
+
+def _f32(t, name, dims):
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float32 and t.dim() == dims):
+        raise ValueError(f"{name} must be a {dims}-D float32 CUDA tensor")
+    return t.contiguous()
+
+
+def _i32(t, name):
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.int32):
+        raise ValueError(f"{name} must be an int32 CUDA tensor")
+    return t.contiguous()
+
+
+def nd_sort(F, n_stop=0, ws=None):
+    """(rank int32[M], front_info int32[4]) of the objective matrix F [M][m]."""
+    F = _f32(F, "F", 2)
+    M, m = F.shape
+    ws = ws or Workspace(F.device)
+    buf = ws.get(workspace_bytes(M, m, 1, M))
+    rank = torch.empty(M, dtype=torch.int32, device=F.device)
+    fi = torch.empty(4, dtype=torch.int32, device=F.device)
+    _check(lib().nsga3_nd_sort(_ptr(F), M, m, int(n_stop), _ptr(rank), _ptr(fi), _ptr(buf),
+                               buf.numel(), _stream(F.device)), "nsga3_nd_sort")
+    return rank, fi
+
+
+def normalize(F, rank, front_info, ws=None):
+    """dict(Fn, ideal, intercept, extreme, degenerate) over S_t."""
+    F = _f32(F, "F", 2)
+    rank, front_info = _i32(rank, "rank"), _i32(front_info, "front_info")
+    M, m = F.shape
+    ws = ws or Workspace(F.device)
+    buf = ws.get(workspace_bytes(M, m, 1, M))
+    dev = F.device
+    Fn = torch.zeros((M, m), dtype=torch.float32, device=dev)
+    ideal = torch.empty(m, dtype=torch.float32, device=dev)
+    icpt = torch.empty(m, dtype=torch.float64, device=dev)
+    ext = torch.empty(m, dtype=torch.int32, device=dev)
+    deg = torch.empty(1, dtype=torch.int32, device=dev)
+    _check(lib().nsga3_normalize(_ptr(F), _ptr(rank), _ptr(front_info), M, m, _ptr(Fn), _ptr(ideal),
+                                 _ptr(icpt), _ptr(ext), _ptr(deg), _ptr(buf), buf.numel(),
+                                 _stream(dev)), "nsga3_normalize")
+    return dict(Fn=Fn, ideal=ideal, intercept=icpt, extreme=ext, degenerate=deg)
+
+
+def associate(Fn, rank, front_info, Z, ws=None):
+    """(pi int32[M], dist float32[M]); -1 outside S_t."""
+    Fn, Z = _f32(Fn, "Fn", 2), _f32(Z, "Z", 2)
+    rank, front_info = _i32(rank, "rank"), _i32(front_info, "front_info")
+    M, m = Fn.shape
+    H = Z.shape[0]
+    if Z.shape[1] != m:
+        raise ValueError("Z must have m columns")
+    ws = ws or Workspace(Fn.device)
+    buf = ws.get(workspace_bytes(M, m, H, M))
+    pi = torch.empty(M, dtype=torch.int32, device=Fn.device)
+    dist = torch.empty(M, dtype=torch.float32, device=Fn.device)
+    _check(lib().nsga3_associate(_ptr(Fn), _ptr(rank), _ptr(front_info), M, m, _ptr(Z), H, _ptr(pi),
+                                 _ptr(dist), _ptr(buf), buf.numel(), _stream(Fn.device)),
+           "nsga3_associate")
+    return pi, dist
+
+
+def niche(rank, front_info, pi, dist, H, N, seed, ws=None):
+    """Ascending selected indices int32[N]."""
+    rank, front_info, pi = _i32(rank, "rank"), _i32(front_info, "front_info"), _i32(pi, "pi")
+    if not (dist.is_cuda and dist.dtype == torch.float32):
+        raise ValueError("dist must be a float32 CUDA tensor")
+    dist = dist.contiguous()
+    M = rank.shape[0]
+    ws = ws or Workspace(rank.device)
+    buf = ws.get(workspace_bytes(M, 2, H, N))
+    sel = torch.empty(int(N), dtype=torch.int32, device=rank.device)
+    _check(lib().nsga3_niche(_ptr(rank), _ptr(front_info), _ptr(pi), _ptr(dist), M, int(H), int(N),
+                             int(seed) & (2**64 - 1), _ptr(sel), _ptr(buf), buf.numel(),
+                             _stream(rank.device)), "nsga3_niche")
+    return sel
+
+
+def select(F, Z, N, seed, ws=None, out=None, intermediates=False):
+    """The whole selection. Returns the ascending selected indices, or with
+    intermediates=True a dict(selected, rank, pi, dist)."""
+    F, Z = _f32(F, "F", 2), _f32(Z, "Z", 2)
+    M, m = F.shape
+    H = Z.shape[0]
+    if Z.shape[1] != m:
+        raise ValueError("Z must have m columns")
+    dev = F.device
+    ws = ws or Workspace(dev)
+    buf = ws.get(workspace_bytes(M, m, H, N))
+    sel = out if out is not None else torch.empty(int(N), dtype=torch.int32, device=dev)
+    rank = pi = dist = None
+    if intermediates:
+        rank = torch.empty(M, dtype=torch.int32, device=dev)
+        pi = torch.empty(M, dtype=torch.int32, device=dev)
+        dist = torch.empty(M, dtype=torch.float32, device=dev)
+    _check(lib().nsga3_select(_ptr(F), M, m, _ptr(Z), H, int(N), int(seed) & (2**64 - 1), _ptr(sel),
+                              _ptr(rank), _ptr(pi), _ptr(dist), _ptr(buf), buf.numel(),
+                              _stream(dev)), "nsga3_select")
+    if intermediates:
+        return dict(selected=sel, rank=rank, pi=pi, dist=dist)
+    return sel
+
+
+def version():
+    return lib().nsga3_version().decode()
