@@ -142,6 +142,20 @@ int nsga3_read_status(const void *ws, void *stream, int32_t *status);
 /* Library version string [host, static storage]. */
 const char *nsga3_version(void);
 
+/* Instrumentation (host, not thread-safe). nsga3_profile_enable(names)
+ * starts recording a pair of HIP events around every later launch of the
+ * named kernels, on the stream of the call that launches them: `names` is a
+ * comma-separated list of kernel names ("dominance", "peel", "associate",
+ * ...), "*" for all, NULL or "" to stop. It creates its event pool up front
+ * (no allocation happens at launch time), clears earlier records and returns
+ * NSGA3_OK, NSGA3_EINVAL (list too long) or NSGA3_EHIP. Up to 8192 launches
+ * are recorded; later ones are counted as dropped.
+ * nsga3_profile_read waits for the recorded events of `kernel` and returns
+ * the summed milliseconds and the number of launches (and the dropped count). */
+int nsga3_profile_enable(const char *names);
+int nsga3_profile_read(const char *kernel, double *total_ms, int64_t *launches,
+                       int32_t *dropped);
+
 #ifdef __cplusplus
 }
 #endif

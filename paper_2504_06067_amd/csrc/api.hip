@@ -23,7 +23,7 @@ Layout make_layout(int M, int m, int H, int N) {
     L.nd = take(Mp * 4);
     L.mask = take(W * Mp * 8);
     L.alive = take(2 * W * 8);
-    L.fcum = take((Mp + 2) * 4);
+    L.facc = take(3 * 33 * 32 * 8);  // front-peeling counter ring
     L.list = take(Mp * 4);
     L.fn = take(Mp * (size_t)m * 4);
     L.rank = take(Mp * 4);
@@ -52,7 +52,7 @@ Ptrs carve(const Layout &L, void *ws) {
     P.nd = (int *)(b + L.nd);
     P.mask = (u64 *)(b + L.mask);
     P.alive = (u64 *)(b + L.alive);
-    P.fcum = (int *)(b + L.fcum);
+    P.facc = (u64 *)(b + L.facc);
     P.list = (int *)(b + L.list);
     P.fn = (float *)(b + L.fn);
     P.rank = (int *)(b + L.rank);
@@ -100,6 +100,50 @@ static int check_ws(const Layout &L, const void *ws, size_t ws_bytes) {
 }
 
 static int to_status(hipError_t e) { return e == hipSuccess ? NSGA3_OK : NSGA3_EHIP; }
+
+// ---------------------------------------------------------- instrumentation
+
+namespace {
+constexpr int PROF_POOL = 8192;   // event pairs per enable
+constexpr int PROF_NAMES = 64;
+struct ProfState {
+    bool on = false;
+    bool all = false;
+    char filter[512] = {0};
+    hipEvent_t ev[2 * PROF_POOL];
+    const char *rec_name[PROF_POOL];
+    int used = 0, created = 0, dropped = 0;
+};
+ProfState g_prof;
+
+bool prof_wanted(const char *name) {
+    if (!g_prof.on) return false;
+    if (g_prof.all) return true;
+    // comma-separated exact names
+    const size_t n = strlen(name);
+    const char *f = g_prof.filter;
+    while (*f) {
+        const char *e = strchr(f, ',');
+        const size_t len = e ? (size_t)(e - f) : strlen(f);
+        if (len == n && strncmp(f, name, n) == 0) return true;
+        if (!e) break;
+        f = e + 1;
+    }
+    return false;
+}
+}  // namespace
+
+ProfScope::ProfScope(const char *name, hipStream_t s) : slot(-1), stream(s) {
+    if (!prof_wanted(name)) return;
+    if (g_prof.used >= g_prof.created) { ++g_prof.dropped; return; }
+    slot = g_prof.used++;
+    g_prof.rec_name[slot] = name;
+    if (hipEventRecord(g_prof.ev[2 * slot], s) != hipSuccess) slot = -1;
+}
+
+ProfScope::~ProfScope() {
+    if (slot >= 0) (void)hipEventRecord(g_prof.ev[2 * slot + 1], stream);
+}
 
 }  // namespace nsga3
 
@@ -205,5 +249,47 @@ int nsga3_read_status(const void *ws, void *stream, int32_t *status) {
 }
 
 const char *nsga3_version(void) { return "nsga3-mi355x 0.1 (gfx950)"; }
+
+int nsga3_profile_enable(const char *kernels) {
+    g_prof.used = 0;
+    g_prof.dropped = 0;
+    if (!kernels || !kernels[0]) {
+        g_prof.on = false;
+        return NSGA3_OK;
+    }
+    if (strlen(kernels) >= sizeof(g_prof.filter)) return NSGA3_EINVAL;
+    strcpy(g_prof.filter, kernels);
+    g_prof.all = strcmp(kernels, "*") == 0;
+    while (g_prof.created < PROF_POOL) {
+        if (hipEventCreate(&g_prof.ev[2 * g_prof.created]) != hipSuccess) return NSGA3_EHIP;
+        if (hipEventCreate(&g_prof.ev[2 * g_prof.created + 1]) != hipSuccess) {
+            (void)hipEventDestroy(g_prof.ev[2 * g_prof.created]);
+            return NSGA3_EHIP;
+        }
+        ++g_prof.created;
+    }
+    g_prof.on = true;
+    return NSGA3_OK;
+}
+
+int nsga3_profile_read(const char *kernel, double *total_ms, int64_t *launches,
+                       int32_t *dropped) {
+    if (!kernel || !total_ms || !launches) return NSGA3_EINVAL;
+    double tot = 0.0;
+    int64_t n = 0;
+    for (int i = 0; i < g_prof.used; ++i) {
+        if (strcmp(g_prof.rec_name[i], kernel) != 0) continue;
+        if (hipEventSynchronize(g_prof.ev[2 * i + 1]) != hipSuccess) return NSGA3_EHIP;
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, g_prof.ev[2 * i], g_prof.ev[2 * i + 1]) != hipSuccess)
+            return NSGA3_EHIP;
+        tot += ms;
+        ++n;
+    }
+    *total_ms = tot;
+    *launches = n;
+    if (dropped) *dropped = g_prof.dropped;
+    return NSGA3_OK;
+}
 
 }  // extern "C"

@@ -133,9 +133,9 @@ hipError_t launch_associate(const Layout &L, const Ptrs &P, const float *Fn, con
                             const int *front_info, const float *Z, int *pi, float *dist,
                             bool reset_status, hipStream_t s) {
     const int M = L.M, m = L.m, H = L.H, Hp = L.Hp;
-    hipLaunchKernelGGL(k_assoc_init, dim3(1), dim3(64), 0, s, P.ctrl, reset_status);
+    NSGA3_LAUNCH("assoc_init", k_assoc_init, dim3(1), dim3(64), 0, s, P.ctrl, reset_status);
     const int nt = M > Hp ? M : Hp;
-    hipLaunchKernelGGL(k_assoc_prep, dim3((nt + 255) / 256), dim3(256), 0, s, Z, H, Hp, m, P.wn,
+    NSGA3_LAUNCH("assoc_prep", k_assoc_prep, dim3((nt + 255) / 256), dim3(256), 0, s, Z, H, Hp, m, P.wn,
                        rank, front_info, M, P.list, P.akey, pi, dist, P.ctrl);
     // slice the references so that the grid holds about 16k waves
     const long long pblocks = (M + 63) / 64;
@@ -148,7 +148,7 @@ hipError_t launch_associate(const Layout &L, const Ptrs &P, const float *Fn, con
     const unsigned blocks = (unsigned)((items + 3) / 4);
 #define NSGA3_ASSOC_CASE(MO)                                                                  \
     case MO:                                                                                  \
-        hipLaunchKernelGGL(k_associate<MO>, dim3(blocks), dim3(256), 0, s, Fn, P.list, P.wn, \
+        NSGA3_LAUNCH("associate", k_associate<MO>, dim3(blocks), dim3(256), 0, s, Fn, P.list, P.wn, \
                            H, Hp, (int)R, nslice, P.akey, P.ctrl);                            \
         break;
     switch (m) {
@@ -159,7 +159,7 @@ hipError_t launch_associate(const Layout &L, const Ptrs &P, const float *Fn, con
         default: return hipErrorInvalidValue;
     }
 #undef NSGA3_ASSOC_CASE
-    hipLaunchKernelGGL(k_assoc_final, dim3((M + 255) / 256), dim3(256), 0, s, P.list, P.akey, H,
+    NSGA3_LAUNCH("assoc_final", k_assoc_final, dim3((M + 255) / 256), dim3(256), 0, s, P.list, P.akey, H,
                        pi, dist, P.ctrl);
     return hipGetLastError();
 }

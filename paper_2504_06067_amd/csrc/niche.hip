@@ -450,20 +450,20 @@ hipError_t launch_niche(const Layout &L, const Ptrs &P, const int *rank, const i
                         bool reset_status, hipStream_t s) {
     const int M = L.M, H = L.H, N = L.N;
     const int nt = M > H ? M : H;
-    hipLaunchKernelGGL(k_niche_init, dim3((nt + 255) / 256), dim3(256), 0, s, H, M, P.rho, P.cnt,
+    NSGA3_LAUNCH("niche_init", k_niche_init, dim3((nt + 255) / 256), dim3(256), 0, s, H, M, P.rho, P.cnt,
                        P.fill, P.picked, P.ctrl, reset_status);
-    hipLaunchKernelGGL(k_niche_count, dim3((M + 255) / 256), dim3(256), 0, s, rank, front_info,
+    NSGA3_LAUNCH("niche_count", k_niche_count, dim3((M + 255) / 256), dim3(256), 0, s, rank, front_info,
                        pi, M, H, P.rho, P.cnt, P.ctrl);
-    hipLaunchKernelGGL(k_niche_plan, dim3(1), dim3(PLAN_THREADS), 0, s, front_info, P.rho, P.cnt,
+    NSGA3_LAUNCH("niche_plan", k_niche_plan, dim3(1), dim3(PLAN_THREADS), 0, s, front_info, P.rho, P.cnt,
                        H, seed, P.off, P.tpick, P.ctrl);
-    hipLaunchKernelGGL(k_niche_scatter, dim3((M + 255) / 256), dim3(256), 0, s, rank, front_info,
+    NSGA3_LAUNCH("niche_scatter", k_niche_scatter, dim3((M + 255) / 256), dim3(256), 0, s, rank, front_info,
                        pi, M, H, P.off, P.fill, P.members);
-    hipLaunchKernelGGL(k_niche_pick, dim3((H + 3) / 4), dim3(256), 0, s, P.rho, P.cnt, P.off,
+    NSGA3_LAUNCH("niche_pick", k_niche_pick, dim3((H + 3) / 4), dim3(256), 0, s, P.rho, P.cnt, P.off,
                        P.tpick, dist, H, seed, P.members, P.remain, P.picked);
     const int ntiles = (M + TILE - 1) / TILE;
-    hipLaunchKernelGGL(k_compact_count, dim3(ntiles), dim3(256), 0, s, rank, front_info, P.picked,
+    NSGA3_LAUNCH("compact_count", k_compact_count, dim3(ntiles), dim3(256), 0, s, rank, front_info, P.picked,
                        M, P.tiles);
-    hipLaunchKernelGGL(k_compact_write, dim3(ntiles), dim3(256), 0, s, rank, front_info, P.picked,
+    NSGA3_LAUNCH("compact_write", k_compact_write, dim3(ntiles), dim3(256), 0, s, rank, front_info, P.picked,
                        P.tiles, ntiles, M, N, selected, P.ctrl);
     return hipGetLastError();
 }

@@ -170,12 +170,12 @@ hipError_t launch_normalize(const Layout &L, const Ptrs &P, const float *F, cons
                             int *extreme, int *degenerate, bool reset_status, hipStream_t s) {
     const int M = L.M, m = L.m;
     const unsigned blocks = (unsigned)((M + 255) / 256);
-    hipLaunchKernelGGL(k_norm_init, dim3(1), dim3(64), 0, s, P.ctrl, m, reset_status);
-    hipLaunchKernelGGL(k_norm_reduce, dim3(blocks), dim3(256), 0, s, F, rank, front_info, M, m,
+    NSGA3_LAUNCH("norm_init", k_norm_init, dim3(1), dim3(64), 0, s, P.ctrl, m, reset_status);
+    NSGA3_LAUNCH("norm_reduce", k_norm_reduce, dim3(blocks), dim3(256), 0, s, F, rank, front_info, M, m,
                        P.list, P.ctrl);
 #define NSGA3_EXT_CASE(MO)                                                                     \
     case MO:                                                                                   \
-        hipLaunchKernelGGL(k_norm_extreme<MO>, dim3(blocks), dim3(256), 0, s, F, P.list, P.ctrl); \
+        NSGA3_LAUNCH("norm_extreme", k_norm_extreme<MO>, dim3(blocks), dim3(256), 0, s, F, P.list, P.ctrl); \
         break;
     switch (m) {
         NSGA3_EXT_CASE(2) NSGA3_EXT_CASE(3) NSGA3_EXT_CASE(4) NSGA3_EXT_CASE(5)
@@ -185,9 +185,9 @@ hipError_t launch_normalize(const Layout &L, const Ptrs &P, const float *F, cons
         default: return hipErrorInvalidValue;
     }
 #undef NSGA3_EXT_CASE
-    hipLaunchKernelGGL(k_norm_solve, dim3(1), dim3(64), 0, s, F, M, m, P.ctrl, ideal, intercept,
+    NSGA3_LAUNCH("norm_solve", k_norm_solve, dim3(1), dim3(64), 0, s, F, M, m, P.ctrl, ideal, intercept,
                        extreme, degenerate);
-    hipLaunchKernelGGL(k_norm_apply, dim3(blocks), dim3(256), 0, s, F, P.list, m, Fn, P.ctrl);
+    NSGA3_LAUNCH("norm_apply", k_norm_apply, dim3(blocks), dim3(256), 0, s, F, P.list, m, Fn, P.ctrl);
     return hipGetLastError();
 }
 

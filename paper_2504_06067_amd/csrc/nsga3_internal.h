@@ -48,7 +48,7 @@ struct Ctrl {
 // Byte offsets of every workspace region (all 256-byte aligned).
 struct Layout {
     int M, m, H, N, Mp, W, Hp;
-    size_t ctrl, ft, nd, mask, alive, fcum, list, fn, rank, pi, dist, akey, wn,
+    size_t ctrl, ft, nd, mask, alive, facc, list, fn, rank, pi, dist, akey, wn,
         rho, cnt, off, fill, tpick, members, picked, remain, tiles, total;
 };
 
@@ -60,7 +60,8 @@ struct Ptrs {
     int *nd;
     u64 *mask;
     u64 *alive;
-    int *fcum, *list;
+    int *list;
+    u64 *facc;
     float *fn;
     int *rank, *pi;
     float *dist;
@@ -165,6 +166,26 @@ __device__ __forceinline__ int load_acquire(const int *p) {
 __device__ __forceinline__ u64 load_acquire(const u64 *p) {
     return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
 }
+
+// ---------------------------------------------------------- instrumentation
+
+// When profiling is enabled for a kernel name, a ProfScope around its launch
+// records a pair of HIP events on the launch stream (events come from a pool
+// created by nsga3_profile_enable; nothing is allocated at launch time).
+struct ProfScope {
+    int slot;
+    hipStream_t stream;
+    ProfScope(const char *name, hipStream_t s);
+    ~ProfScope();
+};
+
+// Enqueue a kernel on stream `s` (which must be in scope), under a ProfScope
+// named after the kernel.
+#define NSGA3_LAUNCH(name, ...)              \
+    do {                                     \
+        ::nsga3::ProfScope ps_(name, s);     \
+        hipLaunchKernelGGL(__VA_ARGS__);     \
+    } while (0)
 
 // -------------------------------------------------------------- launchers
 

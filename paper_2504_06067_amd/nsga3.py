@@ -45,8 +45,10 @@ def lib():
     L.nsga3_select.argtypes = [P, i32, i32, P, i32, i32, u64, P, P, P, P, P, sz, P]
     L.nsga3_read_status.argtypes = [P, P, P]
     L.nsga3_version.restype = ctypes.c_char_p
+    L.nsga3_profile_enable.argtypes = [ctypes.c_char_p]
+    L.nsga3_profile_read.argtypes = [ctypes.c_char_p, P, P, P]
     for f in ("nsga3_nd_sort", "nsga3_normalize", "nsga3_associate", "nsga3_niche",
-              "nsga3_select", "nsga3_read_status"):
+              "nsga3_select", "nsga3_read_status", "nsga3_profile_enable", "nsga3_profile_read"):
         getattr(L, f).restype = i32
     _lib = L
     return L
@@ -194,3 +196,19 @@ def select(F, Z, N, seed, ws=None, out=None, intermediates=False):
 
 def version():
     return lib().nsga3_version().decode()
+
+
+def profile_enable(names):
+    """Record HIP events around launches of the named kernels ("*" = all,
+    None or "" = off)."""
+    _check(lib().nsga3_profile_enable(names.encode() if names else None), "nsga3_profile_enable")
+
+
+def profile_read(kernel):
+    """(total_ms, launches, dropped) recorded for `kernel` since the last enable."""
+    tot = ctypes.c_double(0)
+    n = ctypes.c_int64(0)
+    dropped = ctypes.c_int32(0)
+    _check(lib().nsga3_profile_read(kernel.encode(), ctypes.byref(tot), ctypes.byref(n),
+                                    ctypes.byref(dropped)), "nsga3_profile_read")
+    return tot.value, n.value, dropped.value
