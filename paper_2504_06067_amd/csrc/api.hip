@@ -22,7 +22,13 @@ Layout make_layout(int M, int m, int H, int N) {
     L.ft = take((size_t)m * Mp * 4);
     L.nd = take(Mp * 4);
     L.mask = take(W * Mp * 8);
-    L.alive = take(2 * W * 8);
+    L.rowm = take(W * Mp * 8);
+    L.wit = take(Mp * 4);
+    // alive ring: ns slots of W words, one 128-byte line per word
+    L.ns = (int)((64ull << 20) / (W * 128));
+    if (L.ns > 254) L.ns = 254;
+    if (L.ns < 8) L.ns = 8;
+    L.alive = take((size_t)L.ns * W * 128);
     L.facc = take(3 * 33 * 32 * 8);  // front-peeling counter ring
     L.list = take(Mp * 4);
     L.fn = take(Mp * (size_t)m * 4);
@@ -51,6 +57,8 @@ Ptrs carve(const Layout &L, void *ws) {
     P.ft = (float *)(b + L.ft);
     P.nd = (int *)(b + L.nd);
     P.mask = (u64 *)(b + L.mask);
+    P.rowm = (u64 *)(b + L.rowm);
+    P.wit = (int *)(b + L.wit);
     P.alive = (u64 *)(b + L.alive);
     P.facc = (u64 *)(b + L.facc);
     P.list = (int *)(b + L.list);

@@ -26,6 +26,7 @@ constexpr int PEEL_SHARDS = 32;
 constexpr int PEEL_STRIDE = 32;                       // u64 words between counters (256 B)
 constexpr int PEEL_SLOT = (PEEL_SHARDS + 1) * PEEL_STRIDE;
 constexpr int PEEL_OWN_CAP = 2048;
+constexpr int ALIVE_PAD = 16;  // u64 words per alive word (one 128-byte line)
 
 __global__ void k_nd_init(Ctrl *ctrl, u64 *ring, int *front_info, int n_stop, bool reset_status) {
     for (int i = threadIdx.x; i < 3 * PEEL_SLOT; i += blockDim.x) ring[i] = 0;
@@ -62,7 +63,8 @@ __global__ __launch_bounds__(256) void k_nd_prep(const float *__restrict__ F, in
         if (j < M) rank[j] = NSGA3_UNRANKED;
         if ((j & 63) == 0) {
             int valid = M - j;
-            alive0[j >> 6] = valid >= 64 ? ~0ull : (valid <= 0 ? 0ull : ((1ull << valid) - 1));
+            alive0[(size_t)(j >> 6) * ALIVE_PAD] =
+                valid >= 64 ? ~0ull : (valid <= 0 ? 0ull : ((1ull << valid) - 1));
         }
     }
     if (ballot(bad) != 0 && lane_id() == 0) atomicOr(&ctrl->status, ST_NONFINITE);
@@ -170,7 +172,7 @@ __global__ __launch_bounds__(256) void k_dominance(const float *__restrict__ ft,
     if (cnt_j) atomicAdd(&nd[jglob], cnt_j);
 }
 
-constexpr int PEEL_WAVES = 16;
+constexpr int PEEL_WAVES = 8;
 constexpr int PEEL_UNROLL = 12;
 
 __device__ __forceinline__ u64 load_relaxed(const u64 *p) {
@@ -190,10 +192,16 @@ __device__ __forceinline__ void store_relaxed(int *p, int v) {
 //
 // Chunk c holds the 64 points 64c .. 64c+63. Front 0 is {j : no dominator}
 // (fused counts of the dominance kernel). A point j alive at front k > 0
-// belongs to it iff no alive point dominates it: (mask[w][j] & alive_k[w])
-// == 0 for every word w. The alive sets of consecutive fronts alternate
-// between two bitsets. The peel stops once the ranked fronts hold n_stop
-// points.
+// belongs to it iff no alive point dominates it. Fronts after the first are
+// found with witnesses: every alive point keeps one alive dominator (its
+// witness) and is re-examined only once its witness has been ranked. The
+// re-examination resumes the scan of j's row at the witness's word: the
+// words before it held no alive dominator when they were scanned, and the
+// alive set only shrinks. Over the whole peel each row is read about once.
+// The scans read a row-major copy of the dominance matrix (row j = the W
+// words of point j's dominators), which each workgroup writes for its own
+// chunks when front 1 starts; when front 0 already fills N it is never built.
+// The alive sets of consecutive fronts alternate between two bitsets.
 //
 // Scheduling. While ranking front 0, workgroups claim chunks from a ticket
 // counter until every chunk is claimed; a workgroup then owns its chunks for
@@ -203,109 +211,234 @@ __device__ __forceinline__ void store_relaxed(int *p, int v) {
 // workgroup were full the front-0 wait would time out into an error status.
 //
 // Completion. Per front, chunk c adds (points ranked << 32) + 1 to shard
-// counter c % PEEL_SHARDS; the last chunk of a shard promotes the shard total
-// into the front's top word, which the waiting workgroups poll. Counters live
-// in a ring of three front slots; the slot of front k + 1 is cleared while
-// front k is processed (after front k - 1 completed, nobody reads it).
+// counter c % PEEL_SHARDS (a fire-and-forget atomic); a waiting workgroup
+// reads the 32 shards with one wave and sums them. Counters live in a ring of
+// three front slots; the slot of front k + 1 is cleared while front k is
+// processed (after front k - 1 completed, nobody reads it).
 //
-// Memory ordering. Cross-workgroup words (alive bitsets, counters) are
-// written and read only with agent-scope atomics, which go to the coherent
-// level; each chunk waits for its coherent stores before its counter add, so
-// a workgroup that sees a front complete reads the published alive words.
-// No L2 write-back or invalidation is needed on this path.
+// Memory ordering. Alive words and counters are written with agent-scope
+// atomic stores, which go to the coherent level; each chunk waits for its
+// stores before its counter add. A workgroup polls the counters with relaxed
+// atomic loads, and once a front is complete issues one agent-scope acquire
+// fence, after which ordinary cached loads see the published alive words.
+// The row-major copy and the witnesses of a chunk are touched only by its
+// owner. No L2 write-back is needed on this path.
 //
 // Control flow is wave-uniform around every workgroup barrier: wave 0 makes
 // the scheduling decisions with all its lanes and shares them through LDS.
+constexpr int PEEL_LDS_ALIVE = 2048;  // alive words staged in LDS (M <= 131072)
 
 __device__ __forceinline__ u64 *peel_slot(u64 *ring, int k) { return ring + (size_t)(k % 3) * PEEL_SLOT; }
 
-// Ranks the points of chunk c that are alive at front k and have no alive
-// dominator; publishes the chunk's result. All 16 waves take part.
-__device__ __forceinline__ void peel_chunk(const u64 *__restrict__ mask, const int *__restrict__ nd,
-                                           int Mp, int W, int k, int c, u64 *alive, int *rank,
-                                           u64 *ring, u64 &s_hit) {
+// Alive bitset of front k: slot k % ns of the alive ring; the word of chunk c
+// sits alone on a 128-byte line (ALIVE_PAD words), so no two workgroups ever
+// write the same line and a slot is never cached before it is read.
+__device__ __forceinline__ u64 *alive_slot(u64 *aring, int W, int ns, int k) {
+    return aring + (size_t)(k % ns) * W * ALIVE_PAD;
+}
+
+struct PeelShared {
+    int own[PEEL_OWN_CAP];
+    union {                    // the transpose (front 1 start) and the scans never overlap
+        u64 alive[PEEL_LDS_ALIVE];
+        u64 tile[64][65];
+    };
+    u64 val;
+    u64 need;
+    u64 newly;
+    int flag;
+};
+
+// Row-major copy of chunk c's rows: rowm[j][w] = mask[w][j], through a
+// padded 64 x 64-word LDS tile (coalesced reads and writes).
+__device__ void peel_transpose(const u64 *__restrict__ mask, u64 *__restrict__ rowm, int *wit,
+                               int Mp, int W, int c, PeelShared &sh) {
     const int lane = lane_id();
     const int wv = uniform((int)(threadIdx.x >> 6));
-    const u64 *alive_k = alive + (size_t)(k & 1) * W;
-    u64 *alive_n = alive + (size_t)((k + 1) & 1) * W;
-    const u64 aw = uniform(load_relaxed(&alive_k[c]));
+    for (int w0 = 0; w0 < W; w0 += 64) {
+#pragma unroll
+        for (int q = 0; q < 64 / PEEL_WAVES; ++q) {
+            const int wl = wv * (64 / PEEL_WAVES) + q;
+            const int w = w0 + wl;
+            sh.tile[wl][lane] = (w < W) ? mask[(size_t)w * Mp + (size_t)c * 64 + lane] : 0ull;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < 64 / PEEL_WAVES; ++q) {
+            const int r = wv * (64 / PEEL_WAVES) + q;
+            const int w = w0 + lane;
+            if (w < W) rowm[((size_t)c * 64 + r) * W + w] = sh.tile[lane][r];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < 64) wit[c * 64 + lane] = -1;
+}
+
+// Ranks the points of chunk c that are alive at front k and have no alive
+// dominator; publishes the chunk's result. All 16 waves take part.
+#ifdef NSGA3_PEEL_TRACE
+__device__ u64 *g_trace;
+#define PEEL_MARK(i)                                                                       \
+    if (k == 2 && threadIdx.x == 0)                                                       \
+        g_trace[2 * 16 * W + 8 * c + (i)] = __builtin_amdgcn_s_memrealtime();
+#else
+#define PEEL_MARK(i)
+#endif
+__device__ void peel_chunk(const int *__restrict__ nd, const u64 *__restrict__ rowm, int *wit,
+                           int W, int ns, int k, int c, u64 *alive, int *rank, u64 *ring,
+                           PeelShared &sh) {
+    const int lane = lane_id();
+    const int wv = uniform((int)(threadIdx.x >> 6));
+    const u64 *alive_k = alive_slot(alive, W, ns, k);
+    u64 *alive_n = alive_slot(alive, W, ns, k + 1);
+    const u64 aw = uniform(alive_k[(size_t)c * ALIVE_PAD]);
     const int j = c * 64 + lane;
     u64 newly;
     if (k == 0) {
         newly = aw & ballot(nd[j] == 0);
     } else {
-        __syncthreads();  // every wave has read s_hit of the previous chunk
-        if (wv == 0) s_hit = 0;
+        const bool staged = W <= PEEL_LDS_ALIVE;
+        PEEL_MARK(0)
+        __syncthreads();  // the previous chunk is done with the shared words
+        if (staged && aw != 0)
+            for (int w = threadIdx.x; w < W; w += blockDim.x) sh.alive[w] = alive_k[(size_t)w * ALIVE_PAD];
+        if (wv == 0) sh.newly = 0;
         __syncthreads();
-        if (aw != 0) {
-            bool hit = false;
-            for (int w0 = wv; w0 < W; w0 += PEEL_WAVES * PEEL_UNROLL) {
-                u64 a[PEEL_UNROLL], x[PEEL_UNROLL];
-#pragma unroll
-                for (int u = 0; u < PEEL_UNROLL; ++u) {
-                    const int w = w0 + u * PEEL_WAVES;
-                    a[u] = (w < W) ? load_relaxed(&alive_k[w]) : 0ull;
-                    x[u] = (w < W) ? mask[(size_t)w * Mp + j] : 0ull;
+        PEEL_MARK(1)
+        // points whose witness is still alive stay dominated
+        if (wv == 0) {
+            bool need = false;
+            if ((aw >> lane) & 1ull) {
+                const int wj = wit[j];
+                if (wj < 0) {
+                    need = true;
+                } else {
+                    const u64 word = staged ? sh.alive[wj >> 6] : alive_k[(size_t)(wj >> 6) * ALIVE_PAD];
+                    need = ((word >> (wj & 63)) & 1ull) == 0;
                 }
+            }
+            sh.need = ballot(need);
+        }
+        __syncthreads();
+        PEEL_MARK(2)
+        const u64 need = uniform(sh.need);
+        const int nneed = __popcll(need);
+        // wave wv re-examines the needing points wv, wv + PEEL_WAVES, ... (lane
+        // order); the first 64-word round of all of them is issued at once
+        constexpr int PER = 64 / PEEL_WAVES;
+        int pl[PER], wpos[PER];
+        u64 xr[PER];
+        int mine = 0;
+        {
+            u64 rest = need;
+            for (int skip = 0; skip < wv && rest; ++skip) rest &= rest - 1;
 #pragma unroll
-                for (int u = 0; u < PEEL_UNROLL; ++u) hit |= (a[u] & x[u]) != 0;
-                const u64 hb = ballot(hit) & aw;
-                if (hb) atomicOr(&s_hit, hb);
-                const u64 seen = uniform(__hip_atomic_load(&s_hit, __ATOMIC_RELAXED,
-                                                           __HIP_MEMORY_SCOPE_WORKGROUP)) | hb;
-                if (seen == aw) break;
+            for (int q = 0; q < PER; ++q) {
+                pl[q] = rest ? __ffsll((long long)rest) - 1 : -1;
+                if (rest) {
+                    ++mine;
+                    for (int skip = 0; skip < PEEL_WAVES && rest; ++skip) rest &= rest - 1;
+                }
             }
         }
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            xr[q] = 0;
+            wpos[q] = 0;
+            if (q < mine) {
+                const int jp = c * 64 + pl[q];
+                const int wp = uniform(wit[jp]);
+                wpos[q] = wp < 0 ? 0 : (wp >> 6);
+                const int w = wpos[q] + lane;
+                if (w < W)
+                    xr[q] = rowm[(size_t)jp * W + w] &
+                            (staged ? sh.alive[w] : alive_k[(size_t)w * ALIVE_PAD]);
+            }
+        }
+        for (int q = 0; q < mine; ++q) {
+            const int p = pl[q];
+            const int jp = c * 64 + p;
+            const u64 *row = rowm + (size_t)jp * W;
+            int found = -1;
+            u64 x = xr[q];
+            for (int pos = wpos[q];;) {
+                const u64 b = ballot(x != 0);
+                if (b) {
+                    // new witness: among the alive dominators in the first word that
+                    // has any, the one with the most dominators of its own (a proxy
+                    // for the deepest, which stays alive longest)
+                    const int L = __ffsll((long long)b) - 1;
+                    const unsigned lo = __builtin_amdgcn_readlane((unsigned)x, L);
+                    const unsigned hi = __builtin_amdgcn_readlane((unsigned)(x >> 32), L);
+                    const u64 xl = ((u64)hi << 32) | lo;
+                    const int cand = (pos + L) * 64 + lane;
+                    const bool has = (xl >> lane) & 1ull;
+                    const u64 key = has ? (((u64)(unsigned)nd[cand] << 32) | (unsigned)(~cand)) : 0ull;
+                    const u64 best = wave_max_u64(key);
+                    found = (int)~(unsigned)(best & 0xffffffffull);
+                    break;
+                }
+                pos += 64;
+                if (pos >= W) break;
+                const int w = pos + lane;
+                x = 0;
+                if (w < W) x = row[w] & (staged ? sh.alive[w] : alive_k[(size_t)w * ALIVE_PAD]);
+            }
+            if (lane == 0) wit[jp] = found;
+            if (found < 0 && lane == 0) atomicOr(&sh.newly, 1ull << p);
+        }
         __syncthreads();
-        newly = aw & ~uniform(s_hit);
+        PEEL_MARK(3)
+        newly = aw & uniform(sh.newly);
     }
     if (wv == 0) {
-        if ((newly >> lane) & 1ull) rank[j] = k;  // read only by later kernels
-        store_relaxed(&alive_n[c], aw & ~newly);
+        store_relaxed(&alive_n[(size_t)c * ALIVE_PAD], aw & ~newly);
         __builtin_amdgcn_s_waitcnt(0);
         u64 *slot = peel_slot(ring, k);
-        const int sh = c % PEEL_SHARDS;
         const u64 add = ((u64)__popcll(newly) << 32) | 1ull;
-        const u64 old = uniform(__hip_atomic_fetch_add(&slot[sh * PEEL_STRIDE], lane == 0 ? add : 0ull,
-                                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-        const unsigned shard_chunks = (unsigned)((W - sh + PEEL_SHARDS - 1) / PEEL_SHARDS);
-        if ((unsigned)(old & 0xffffffffull) + 1u == shard_chunks) {
-            // last chunk of this shard: promote the shard total
-            const u64 total = (((old >> 32) + (u64)__popcll(newly)) << 32) | 1ull;
-            __hip_atomic_fetch_add(&slot[PEEL_SHARDS * PEEL_STRIDE], lane == 0 ? total : 0ull,
-                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(&slot[(c % PEEL_SHARDS) * PEEL_STRIDE], lane == 0 ? add : 0ull,
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if ((newly >> lane) & 1ull) rank[j] = k;  // read only by later kernels
+#ifdef NSGA3_PEEL_TRACE
+        if (k == 2 && lane == 0) {
+            g_trace[2 * 16 * W + 8 * c + 4] = __builtin_amdgcn_s_memrealtime();
+            g_trace[2 * 16 * W + 8 * c + 5] = blockIdx.x;
+            g_trace[2 * 16 * W + 8 * c + 6] = __popcll(uniform(sh.need));
         }
+#endif
     }
 }
 
-__global__ __launch_bounds__(1024) void k_peel(const u64 *__restrict__ mask,
+__global__ __launch_bounds__(64 * PEEL_WAVES) void k_peel(const u64 *__restrict__ mask,
                                                 const int *__restrict__ nd, int M, int Mp, int W,
-                                                int n_stop, u64 *alive, int *rank, u64 *ring,
-                                                Ctrl *ctrl, int *front_info
+                                                int n_stop, int ns, u64 *alive, int *rank,
+                                                u64 *ring, u64 *rowm, int *wit, Ctrl *ctrl,
+                                                int *front_info
 #ifdef NSGA3_PEEL_TRACE
                                                 , u64 *trace
 #endif
                                                 ) {
-    __shared__ int s_own[PEEL_OWN_CAP];
-    __shared__ u64 s_hit;
-    __shared__ u64 s_val;
-    __shared__ int s_flag;
+    __shared__ PeelShared sh;
+#ifdef NSGA3_PEEL_TRACE
+    g_trace = trace;
+#endif
+    // drop cached lines of alive slots read by an earlier call on this workspace
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     const int lane = lane_id();
     const int wv = uniform((int)(threadIdx.x >> 6));
     const u64 one = lane == 0 ? 1ull : 0ull;
-    const unsigned shards_used = (unsigned)(W < PEEL_SHARDS ? W : PEEL_SHARDS);
 
     // front 0: claim and rank chunks until all are claimed
     int nown = 0;
     for (;;) {
-        if (wv == 0) s_val = uniform(atomicAdd(&ctrl->ticket, one));
+        if (wv == 0) sh.val = uniform(atomicAdd(&ctrl->ticket, one));
         __syncthreads();
-        const u64 t = uniform(s_val);
+        const u64 t = uniform(sh.val);
         __syncthreads();
         if (t >= (u64)W) break;
         const int c = (int)t;
-        peel_chunk(mask, nd, Mp, W, 0, c, alive, rank, ring, s_hit);
-        if (wv == 0) s_own[nown] = c;
+        peel_chunk(nd, rowm, wit, W, ns, 0, c, alive, rank, ring, sh);
+        if (wv == 0) sh.own[nown] = c;
         ++nown;
         if (nown == PEEL_OWN_CAP) break;
     }
@@ -318,21 +451,26 @@ __global__ __launch_bounds__(1024) void k_peel(const u64 *__restrict__ mask,
     for (int k = 1;; ++k) {
         // wait for front k - 1
         if (wv == 0) {
-            const u64 *top = peel_slot(ring, k - 1) + PEEL_SHARDS * PEEL_STRIDE;
+            const u64 *slot = peel_slot(ring, k - 1);
             u64 v = 0;
             int ok = 1;
             for (unsigned polls = 0;; ++polls) {
-                v = uniform(load_relaxed(top));
-                if ((unsigned)(v & 0xffffffffull) >= shards_used) break;
+                // lanes 0..31 read one shard each; the wave sums (count, size)
+                u64 part = lane < PEEL_SHARDS ? load_relaxed(&slot[lane * PEEL_STRIDE]) : 0ull;
+                v = uniform(wave_sum(part));
+                if ((unsigned)(v & 0xffffffffull) >= (unsigned)W) break;
                 if (polls == (1u << 26)) { ok = 0; break; }
                 __builtin_amdgcn_s_sleep(2);
             }
-            s_val = v;
-            s_flag = ok;
+            sh.val = v;
+            sh.flag = ok;
         }
         __syncthreads();
-        const u64 v = uniform(s_val);
-        const int ok = uniform(s_flag);
+        const u64 v = uniform(sh.val);
+        const int ok = uniform(sh.flag);
+        // alive slots are reused only after ns fronts: then cached copies of the
+        // slot read ns fronts ago must be dropped before it is read again
+        if (k + 1 >= ns) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         __syncthreads();
         const int size = (int)(v >> 32);
         const int prev = cum;
@@ -351,12 +489,14 @@ __global__ __launch_bounds__(1024) void k_peel(const u64 *__restrict__ mask,
         // this workgroup's own front-k publish, which front k + 1 waits for, is
         // ordered after these stores
         if (wv == 0 && lane <= PEEL_SHARDS) store_relaxed(&peel_slot(ring, k + 1)[lane * PEEL_STRIDE], 0ull);
+        if (k == 1)
+            for (int q = 0; q < nown; ++q) peel_transpose(mask, rowm, wit, Mp, W, uniform(sh.own[q]), sh);
         for (int q = 0; q < nown; ++q) {
-            const int c = uniform(s_own[q]);
+            const int c = uniform(sh.own[q]);
 #ifdef NSGA3_PEEL_TRACE
             if (threadIdx.x == 0 && k < 16) trace[2 * (k * W + c)] = __builtin_amdgcn_s_memrealtime();
 #endif
-            peel_chunk(mask, nd, Mp, W, k, c, alive, rank, ring, s_hit);
+            peel_chunk(nd, rowm, wit, W, ns, k, c, alive, rank, ring, sh);
 #ifdef NSGA3_PEEL_TRACE
             if (threadIdx.x == 0 && k < 16) trace[2 * (k * W + c) + 1] = __builtin_amdgcn_s_memrealtime();
 #endif
@@ -388,9 +528,9 @@ hipError_t launch_nd_sort(const Layout &L, const Ptrs &P, const float *F, int n_
         default: return hipErrorInvalidValue;
     }
 #undef NSGA3_DOM_CASE
-    const int peel_blocks = W < 2 * device_info().cus ? W : 2 * device_info().cus;
+    const int peel_blocks = W < 3 * device_info().cus ? W : 3 * device_info().cus;
     NSGA3_LAUNCH("peel", k_peel, dim3(peel_blocks), dim3(64 * PEEL_WAVES), 0, s, P.mask, P.nd, M,
-                 Mp, W, n_stop, P.alive, rank, P.facc, P.ctrl, front_info
+                 Mp, W, n_stop, L.ns, P.alive, rank, P.facc, P.rowm, P.wit, P.ctrl, front_info
 #ifdef NSGA3_PEEL_TRACE
                  , P.akey
 #endif

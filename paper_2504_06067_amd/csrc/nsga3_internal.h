@@ -47,8 +47,8 @@ struct Ctrl {
 
 // Byte offsets of every workspace region (all 256-byte aligned).
 struct Layout {
-    int M, m, H, N, Mp, W, Hp;
-    size_t ctrl, ft, nd, mask, alive, facc, list, fn, rank, pi, dist, akey, wn,
+    int M, m, H, N, Mp, W, Hp, ns;
+    size_t ctrl, ft, nd, mask, rowm, wit, alive, facc, list, fn, rank, pi, dist, akey, wn,
         rho, cnt, off, fill, tpick, members, picked, remain, tiles, total;
 };
 
@@ -59,6 +59,8 @@ struct Ptrs {
     float *ft;
     int *nd;
     u64 *mask;
+    u64 *rowm;
+    int *wit;
     u64 *alive;
     int *list;
     u64 *facc;
@@ -130,6 +132,15 @@ __device__ __forceinline__ u64 wave_min_u64(u64 v) {
     for (int o = 32; o > 0; o >>= 1) {
         u64 w = __shfl_xor(v, o, 64);
         v = w < v ? w : v;
+    }
+    return v;
+}
+
+__device__ __forceinline__ u64 wave_max_u64(u64 v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        u64 w = __shfl_xor(v, o, 64);
+        v = w > v ? w : v;
     }
     return v;
 }
