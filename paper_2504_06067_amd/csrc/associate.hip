@@ -70,6 +70,26 @@ __global__ __launch_bounds__(256) void k_assoc_prep(const float *__restrict__ Z,
 
 // Work item = (block of 64 list entries, slice of R references). Grid covers
 // the largest possible S_t; items past the actual list length exit at once.
+// The reference loop reads the unit directions through the scalar cache
+// (the item is wave-uniform) and is unrolled by four.
+template <int MO>
+__device__ __forceinline__ void assoc_ref(const float (&f)[MO], const float *__restrict__ wn,
+                                          int Hp, int j, float &best, int &bj) {
+    float w[MO];
+#pragma unroll
+    for (int k = 0; k < MO; ++k) w[k] = wn[(size_t)k * Hp + j];
+    float p = f[0] * w[0];
+#pragma unroll
+    for (int k = 1; k < MO; ++k) p = fmaf(f[k], w[k], p);
+    float d2 = 0.0f;
+#pragma unroll
+    for (int k = 0; k < MO; ++k) {
+        const float r = fmaf(-p, w[k], f[k]);
+        d2 = fmaf(r, r, d2);
+    }
+    if (d2 < best) { best = d2; bj = j; }
+}
+
 template <int MO>
 __global__ __launch_bounds__(256) void k_associate(const float *__restrict__ Fn,
                                                     const int *__restrict__ list,
@@ -77,7 +97,7 @@ __global__ __launch_bounds__(256) void k_associate(const float *__restrict__ Fn,
                                                     int R, int nslice, u64 *__restrict__ akey,
                                                     const Ctrl *__restrict__ ctrl) {
     const int n = ctrl->list_count;
-    const long long item = (long long)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const long long item = uniform((long long)blockIdx.x * 4 + (threadIdx.x >> 6));
     const int pb = (int)(item / nslice);
     const int sl = (int)(item % nslice);
     if (pb * 64 >= n) return;
@@ -91,21 +111,14 @@ __global__ __launch_bounds__(256) void k_associate(const float *__restrict__ Fn,
     const int h1 = min(h0 + R, H);
     float best = INFINITY;
     int bj = h0;
-    for (int j = h0; j < h1; ++j) {
-        float w[MO];
-#pragma unroll
-        for (int k = 0; k < MO; ++k) w[k] = wn[(size_t)k * Hp + j];
-        float p = f[0] * w[0];
-#pragma unroll
-        for (int k = 1; k < MO; ++k) p = fmaf(f[k], w[k], p);
-        float d2 = 0.0f;
-#pragma unroll
-        for (int k = 0; k < MO; ++k) {
-            const float r = fmaf(-p, w[k], f[k]);
-            d2 = fmaf(r, r, d2);
-        }
-        if (d2 < best) { best = d2; bj = j; }
+    int j = h0;
+    for (; j + 4 <= h1; j += 4) {
+        assoc_ref<MO>(f, wn, Hp, j, best, bj);
+        assoc_ref<MO>(f, wn, Hp, j + 1, best, bj);
+        assoc_ref<MO>(f, wn, Hp, j + 2, best, bj);
+        assoc_ref<MO>(f, wn, Hp, j + 3, best, bj);
     }
+    for (; j < h1; ++j) assoc_ref<MO>(f, wn, Hp, j, best, bj);
     if (in && h0 < h1) {
         const u64 key = ((u64)__float_as_uint(best) << 32) | (unsigned)bj;
         atomicMin(&akey[x], key);

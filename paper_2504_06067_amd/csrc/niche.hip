@@ -71,6 +71,21 @@ __device__ __forceinline__ long long block_sum_ll(long long v, long long *red) {
     return uniform(s);
 }
 
+// Per-thread cache of the references a plan thread owns (contiguous ranges of
+// up to PLAN_PER references; larger H falls back to global reads).
+constexpr int PLAN_PER = 12;
+
+__device__ __forceinline__ long long block_max_ll(long long v, long long *red) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = max(v, (long long)__shfl_xor(v, o, 64));
+    __syncthreads();
+    if (lane_id() == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    long long m = 0;
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) m = max(m, red[i]);
+    return uniform(m);
+}
+
 __global__ __launch_bounds__(PLAN_THREADS) void k_niche_plan(const int *__restrict__ front_info,
                                                               const int *__restrict__ rho,
                                                               const int *__restrict__ cnt, int H,
@@ -85,11 +100,39 @@ __global__ __launch_bounds__(PLAN_THREADS) void k_niche_plan(const int *__restri
     const int lane = lane_id();
     const int K = uniform(front_info[2]);
 
-    // exclusive scan of c over contiguous per-thread ranges
+    // thread tid owns the contiguous references [b0, b1)
     const int per = (H + PLAN_THREADS - 1) / PLAN_THREADS;
     const int b0 = min(tid * per, H), b1 = min(b0 + per, H);
+    const bool cached = per <= PLAN_PER;
+    int rc[PLAN_PER], cc[PLAN_PER];
+#pragma unroll
+    for (int q = 0; q < PLAN_PER; ++q) {
+        const int j = b0 + q;
+        const bool in = cached && j < b1;
+        rc[q] = in ? rho[j] : 0;
+        cc[q] = in ? cnt[j] : 0;
+    }
+    // Loops over the owned references: compile-time indices into the register
+    // cache when H fits, a plain loop over global memory otherwise.
+#define PLAN_FOR(BODY)                                                         \
+    if (cached) {                                                              \
+        _Pragma("unroll") for (int q = 0; q < PLAN_PER; ++q) {                 \
+            const int j = b0 + q;                                              \
+            if (j < b1) {                                                      \
+                const int cj = cc[q], rj = rc[q];                              \
+                BODY                                                           \
+            }                                                                  \
+        }                                                                      \
+    } else {                                                                   \
+        for (int j = b0; j < b1; ++j) {                                        \
+            const int cj = cnt[j], rj = rho[j];                                \
+            BODY                                                               \
+        }                                                                      \
+    }
+
+    // exclusive scan of c
     int local = 0;
-    for (int j = b0; j < b1; ++j) local += cnt[j];
+    PLAN_FOR({ (void)rj; local += cj; })
     part[tid] = local;
     __syncthreads();
     if (wv == 0) {
@@ -106,18 +149,18 @@ __global__ __launch_bounds__(PLAN_THREADS) void k_niche_plan(const int *__restri
     }
     __syncthreads();
     int run = part[tid];
-    for (int j = b0; j < b1; ++j) {
+    long long hi_local = 0;
+    PLAN_FOR({
         off[j] = run;
-        run += cnt[j];
-    }
+        run += cj;
+        if (cj > 0) hi_local = max(hi_local, (long long)rj + cj);
+    })
     if (b1 == H && b0 < b1) off[H] = run;
-    long long total = 0;
-    for (int j = tid; j < H; j += PLAN_THREADS) total += cnt[j];
-    total = block_sum_ll(total, red);
+    const long long total = block_sum_ll((long long)local, red);
 
     if (K >= total) {
         // the whole last front is taken
-        for (int j = tid; j < H; j += PLAN_THREADS) tpick[j] = cnt[j];
+        PLAN_FOR({ (void)rj; tpick[j] = cj; })
         if (wv == 0) {
             ctrl->all_pick = 1;
             ctrl->lstar = -1;
@@ -128,46 +171,57 @@ __global__ __launch_bounds__(PLAN_THREADS) void k_niche_plan(const int *__restri
         return;
     }
     // L* = max{L : P(L) <= K}; P(0) = 0 <= K < total = P(hi)
-    long long hi_l = 0;
-    for (int j = tid; j < H; j += PLAN_THREADS)
-        if (cnt[j] > 0) hi_l = max(hi_l, (long long)rho[j] + cnt[j]);
-    {
-        // block-wide maximum
-        long long v = hi_l;
-        for (int o = 32; o > 0; o >>= 1) v = max(v, (long long)__shfl_xor(v, o, 64));
-        __syncthreads();
-        if (lane_id() == 0) red[tid >> 6] = v;
-        __syncthreads();
-        hi_l = 0;
-        for (int i = 0; i < PLAN_THREADS / 64; ++i) hi_l = max(hi_l, red[i]);
-        hi_l = uniform(hi_l);
-    }
-    long long lo = 0, hi = hi_l;
+    long long lo = 0, hi = block_max_ll(hi_local, red);
     while (hi - lo > 1) {
         const long long mid = (lo + hi) >> 1;
         long long p = 0;
-        for (int j = tid; j < H; j += PLAN_THREADS)
-            p += min((long long)cnt[j], max(0ll, mid - rho[j]));
+        PLAN_FOR({ p += min((long long)cj, max(0ll, mid - rj)); })
         p = block_sum_ll(p, red);
         if (p <= K) lo = mid; else hi = mid;
     }
     const int Ls = (int)lo;
     long long pl = 0;
-    for (int j = tid; j < H; j += PLAN_THREADS) pl += min((long long)cnt[j], max(0ll, (long long)Ls - rho[j]));
+    int tcount = 0;
+    PLAN_FOR({
+        pl += min((long long)cj, max(0ll, (long long)Ls - rj));
+        tcount += (cj > 0 && rj <= Ls && Ls < rj + cj);
+    })
     pl = block_sum_ll(pl, red);
     const int r = (int)(K - pl);
+    const long long tsize = block_sum_ll((long long)tcount, red);
 
-    // radix select (8 bits per pass, most significant first) of the r-th least
-    // key among T; keys of distinct references differ (sm64 is a bijection)
-    u64 prefix = 0, pmask = 0;
-    int need = r;
-    if (r > 0) {
+    // the r least tag-1 keys of T = {j : rho_j <= L* < rho_j + c_j} get one more
+    // pick: radix select (8 bits per pass, most significant first) of the r-th
+    // least key; keys of distinct references differ (sm64 is a bijection)
+    u64 prefix = ~0ull;  // r == |T|: every key qualifies
+    if (r > 0 && r < tsize) {
+        u64 kc[PLAN_PER];
+#pragma unroll
+        for (int q = 0; q < PLAN_PER; ++q) {
+            const int j = b0 + q;
+            kc[q] = 0ull;
+            if (cached && j < b1 && cc[q] > 0 && rc[q] <= Ls && Ls < rc[q] + cc[q])
+                kc[q] = tie_key(seed, 1u, (unsigned)j, (unsigned)Ls);
+        }
+        prefix = 0;
+        u64 pmask = 0;
+        int need = r;
         for (int pass = 0; pass < 8; ++pass) {
             const int shift = 56 - 8 * pass;
             for (int q = tid; q < 256; q += PLAN_THREADS) hist[q] = 0;
             __syncthreads();
-            for (int j = tid; j < H; j += PLAN_THREADS) {
-                if (cnt[j] > 0 && rho[j] <= Ls && Ls < rho[j] + cnt[j]) {
+            if (cached) {
+#pragma unroll
+                for (int q = 0; q < PLAN_PER; ++q) {
+                    const int j = b0 + q;
+                    const bool inT = j < b1 && cc[q] > 0 && rc[q] <= Ls && Ls < rc[q] + cc[q];
+                    if (inT && (kc[q] & pmask) == prefix)
+                        atomicAdd(&hist[(kc[q] >> shift) & 255u], 1u);
+                }
+            } else {
+                for (int j = b0; j < b1; ++j) {
+                    const bool inT = cnt[j] > 0 && rho[j] <= Ls && Ls < rho[j] + cnt[j];
+                    if (!inT) continue;
                     const u64 kj = tie_key(seed, 1u, (unsigned)j, (unsigned)Ls);
                     if ((kj & pmask) == prefix) atomicAdd(&hist[(kj >> shift) & 255u], 1u);
                 }
@@ -200,13 +254,14 @@ __global__ __launch_bounds__(PLAN_THREADS) void k_niche_plan(const int *__restri
             __syncthreads();
         }
     }
-    for (int j = tid; j < H; j += PLAN_THREADS) {
-        int t = (int)min((long long)cnt[j], max(0ll, (long long)Ls - rho[j]));
-        if (r > 0 && cnt[j] > 0 && rho[j] <= Ls && Ls < rho[j] + cnt[j] &&
-            tie_key(seed, 1u, (unsigned)j, (unsigned)Ls) <= prefix)
+    PLAN_FOR({
+        int t = (int)min((long long)cj, max(0ll, (long long)Ls - rj));
+        if (r > 0 && cj > 0 && rj <= Ls && Ls < rj + cj &&
+            (prefix == ~0ull || tie_key(seed, 1u, (unsigned)j, (unsigned)Ls) <= prefix))
             t += 1;
         tpick[j] = t;
-    }
+    })
+#undef PLAN_FOR
     if (wv == 0) {
         ctrl->all_pick = 0;
         ctrl->lstar = Ls;
