@@ -38,6 +38,8 @@ def parse():
     ap.add_argument("--workload", default="large", choices=["small", "large", "many_objective"])
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--batched-reps", type=int, default=20)
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target CPU time of the oracle sample")
     return ap.parse_args()
@@ -63,6 +65,92 @@ def cpu_baseline(inst, target_s):
         "kind": "oracle",
         "sample": f"{n} full selection(s) of the same instance (2N={inst['M']}, m={inst['m']}, "
                   f"H={inst['H']}) after one untimed run; {el:.1f} s single-threaded FP64 C",
+    }
+
+
+def _median_ms(fn, reps, stream):
+    import numpy as np
+    import torch
+
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(reps)]
+    for a, b in ev:
+        a.record(stream)
+        fn()
+        b.record(stream)
+    torch.cuda.synchronize()
+    t = np.array([a.elapsed_time(b) for a, b in ev])
+    return float(np.median(t)), float(np.percentile(t, 99))
+
+
+def bench_batched(args, dev):
+    """64 uneven instances: one graph replay of the batched call against the
+    same 64 instances as back-to-back plain calls (with and without a host
+    sync after each). Throughput counts merged solutions of all instances."""
+    import torch
+
+    from paper_2504_06067_amd import nsga3, workloads
+
+    insts = workloads.batched_instances(args.seed, 64)
+    total = sum(q["M"] for q in insts)
+    probs = [dict(F=torch.from_numpy(q["F"]).to(dev), Z=torch.from_numpy(q["Z"]).to(dev),
+                  N=q["N"], seed=q["seed"]) for q in insts]
+    stream = torch.cuda.current_stream(dev)
+    bt = nsga3.Batch(probs)
+    for _ in range(3):
+        bt.run()
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream(dev)
+    side.wait_stream(stream)
+    with torch.cuda.stream(side):
+        bt.run()
+    stream.wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        bt.run()
+    graph.replay()
+    torch.cuda.synchronize()
+    if bt.status() != [nsga3.OK] * len(insts):
+        raise RuntimeError("batched status not OK")
+    g_med, g_p99 = _median_ms(graph.replay, args.batched_reps, stream)
+    e_med, _ = _median_ms(bt.run, args.batched_reps, stream)
+
+    wss = [nsga3.Workspace(dev) for _ in probs]
+    outs = [torch.empty(p["N"], dtype=torch.int32, device=dev) for p in probs]
+
+    def plain():
+        for p, w, o in zip(probs, wss, outs):
+            nsga3.select(p["F"], p["Z"], p["N"], p["seed"], ws=w, out=o)
+
+    def plain_sync():
+        for p, w, o in zip(probs, wss, outs):
+            nsga3.select(p["F"], p["Z"], p["N"], p["seed"], ws=w, out=o)
+            torch.cuda.synchronize()
+
+    plain()
+    torch.cuda.synchronize()
+    p_med, _ = _median_ms(plain, max(3, args.batched_reps // 2), stream)
+    t0 = time.perf_counter()
+    reps = max(3, args.batched_reps // 4)
+    for _ in range(reps):
+        plain_sync()
+    ps_ms = (time.perf_counter() - t0) * 1e3 / reps
+    for w in wss:
+        if w.status() != nsga3.OK:
+            raise RuntimeError("plain status not OK")
+    return {
+        "workload": "64 uneven instances, 2N log-uniform [2000, 40000], m in {3,5,8,10}, "
+                    f"sum 2N = {total}",
+        "graph_ms": {"p50": g_med, "p99": g_p99},
+        "batched_eager_ms": e_med,
+        "plain_back_to_back_ms": p_med,
+        "plain_synced_ms": ps_ms,
+        "value": total / (g_med / 1e3),
+        "plain_value": total / (p_med / 1e3),
+        "unit": "merged solutions/s",
+        "speedup_vs_plain": p_med / g_med,
+        "speedup_vs_plain_synced": ps_ms / g_med,
     }
 
 
@@ -149,6 +237,8 @@ def main():
             "launches_timed": dom_n,
         },
     }
+    if not args.no_batched:
+        res["batched"] = bench_batched(args, dev)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(inst, args.cpu_seconds)
     print(json.dumps(res), flush=True)

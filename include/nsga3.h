@@ -28,6 +28,7 @@
  *  - `ws` is a device buffer of at least nsga3_workspace_bytes(M, m, H, N)
  *    bytes, 256-byte aligned. Calls that overlap in time need distinct
  *    workspaces. The status word reflects the most recent call on `ws`.
+ *    Nothing in `ws` carries over from one call to the next.
  *  - Ranks are 0-based (the paper's first front F_1 is rank 0). Points in
  *    fronts after the last selected front l are NSGA3_UNRANKED.
  *  - front_info is int32[4] = {l, |S|, K, fronts ranked}: S is the union of
@@ -134,6 +135,51 @@ int nsga3_select(const float *F, int32_t M, int32_t m, const float *Z, int32_t H
                  int32_t N, uint64_t seed, int32_t *selected, int32_t *rank_out,
                  int32_t *pi_out, float *dist_out,
                  void *ws, size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------- batching
+ * Many independent selections in one call: every stage runs once over all
+ * instances (one grid per kernel, instances of equal m share a launch), so
+ * small and uneven instances fill the GPU together. Each instance's result
+ * is bit-identical to a plain nsga3_select on the same arguments, whatever
+ * the batch around it and whatever its tile parameters.
+ *
+ * The instance array is [host] memory, read during the call only: the call
+ * writes the descriptors into the workspace with its own kernels, so the
+ * whole call is a sequence of kernel launches on `stream` (capturable in a
+ * HIP graph; a replay reuses the captured descriptors and shapes). */
+#define NSGA3_MAX_BATCH 1024
+
+typedef struct nsga3_instance {
+    const float *F;       /* [M][m] float32 objectives (read) */
+    const float *Z;       /* [H][m] float32 reference points (read) */
+    int32_t *selected;    /* int32[N] (write): selected indices, ascending */
+    int32_t *rank;        /* int32[M] (write) or NULL: ranks as nsga3_nd_sort */
+    int32_t *pi;          /* int32[M] (write) or NULL: reference of each point of S_t */
+    float *dist;          /* float32[M] (write) or NULL: its perpendicular distance */
+    int32_t M, m, H, N;   /* as nsga3_select */
+    uint64_t seed;        /* tie-break seed, as nsga3_select */
+    int32_t tile[4];      /* tile parameters, 0 = automatic: [0] column tiles of 64
+                           * points per dominance work item (1..64), [1] references
+                           * per association slice (16..H, multiple of 16 unless H);
+                           * [2], [3] must be 0. Results do not depend on them. */
+} nsga3_instance;
+
+/* Workspace bytes for a batch of B instances [host array]; 0 if any instance
+ * or B (1..NSGA3_MAX_BATCH) would be rejected. Pure host function. */
+size_t nsga3_batched_workspace_bytes(const nsga3_instance *inst, int32_t B);
+
+/* nsga3_select for every instance of inst[0..B) [host array]. Instances must
+ * not share output buffers. Returns NSGA3_EINVAL, with nothing enqueued, for
+ * a bad instance, B out of range or a bad tile parameter; NSGA3_EWORKSPACE
+ * if ws_bytes is below nsga3_batched_workspace_bytes. */
+int nsga3_select_batched(const nsga3_instance *inst, int32_t B, void *ws, size_t ws_bytes,
+                         void *stream);
+
+/* Waits for `stream`, then reads the status of every instance of the last
+ * batched call on `ws` into status[0..B) [host], each as nsga3_read_status.
+ * `inst` and B must be those of that call. */
+int nsga3_read_status_batched(const nsga3_instance *inst, int32_t B, const void *ws,
+                              void *stream, int32_t *status);
 
 /* Waits for `stream`, then reads the status word of `ws` into *status [host]
  * (NSGA3_OK, NSGA3_ENONFINITE, NSGA3_EINVAL or NSGA3_EINTERNAL). Returns

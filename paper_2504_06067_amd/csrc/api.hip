@@ -1,7 +1,16 @@
-// C-ABI entry points of libnsga3: host-side validation, workspace carving and
-// the ordered enqueue of each stage's kernels. No call allocates memory or
-// waits for the device, except nsga3_read_status (which waits by design).
+// C-ABI entry points of libnsga3: host-side validation, workspace carving,
+// the batch plan, and the ordered enqueue of each stage's kernels. No call
+// allocates device memory or waits for the device, except the status reads
+// (which wait by design).
+//
+// Workspace of a call with B instances: the instance regions one after the
+// other (instance 0 at offset 0, so its control block, and the status word,
+// sit at the start of the workspace), then the batch header (descriptors and
+// prefix arrays), which the call's first kernels write from their arguments.
 #include <string.h>
+
+#include <algorithm>
+#include <vector>
 
 #include "nsga3_internal.h"
 
@@ -29,7 +38,7 @@ Layout make_layout(int M, int m, int H, int N) {
     if (L.ns > 254) L.ns = 254;
     if (L.ns < 8) L.ns = 8;
     L.alive = take((size_t)L.ns * W * 128);
-    L.facc = take(3 * 33 * 32 * 8);  // front-peeling counter ring
+    L.facc = take(3 * PEEL_SLOT * 8);  // front-peeling counter ring
     L.list = take(Mp * 4);
     L.fn = take(Mp * (size_t)m * 4);
     L.rank = take(Mp * 4);
@@ -101,13 +110,284 @@ static bool valid_shape(int M, int m, int H, int N) {
 
 static bool aligned(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
 
-static int check_ws(const Layout &L, const void *ws, size_t ws_bytes) {
+static int to_status(hipError_t e) { return e == hipSuccess ? NSGA3_OK : NSGA3_EHIP; }
+
+// ------------------------------------------------------------ batch header
+
+// Byte offsets inside the batch header.
+struct HeaderLayout {
+    size_t tab, pt_pref, ref_pref, chunk_pref, tile_pref, order, dom_pref, asc_pref, ticket, total;
+};
+
+static HeaderLayout header_layout(int B) {
+    HeaderLayout h;
+    size_t o = 0;
+    auto take = [&o](size_t bytes) { size_t at = o; o += up256(bytes); return at; };
+    h.tab = take((size_t)B * sizeof(Inst));
+    h.pt_pref = take((size_t)(B + 1) * 4);
+    h.ref_pref = take((size_t)(B + 1) * 4);
+    h.chunk_pref = take((size_t)(B + 1) * 4);
+    h.tile_pref = take((size_t)(B + 1) * 4);
+    h.order = take((size_t)B * 4);
+    h.dom_pref = take((size_t)(B + 1) * 8);
+    h.asc_pref = take((size_t)(B + 1) * 8);
+    h.ticket = take(8);
+    h.total = o;
+    return h;
+}
+
+// Association slicing: references per slice so that the whole batch holds
+// about ASSOC_WAVES waves (a lone large instance gets many slices, a large
+// batch whole reference sets per wave).
+constexpr long long ASSOC_WAVES = 16384;
+
+static int auto_slice(int H, long long sum_W) {
+    long long R = (long long)H * sum_W / ASSOC_WAVES;
+    R = ((R + 15) / 16) * 16;
+    if (R < 32) R = 32;
+    if (R > H) R = H;
+    return (int)R;
+}
+
+// One instance's shape and caller pointers, before placement.
+struct Spec {
+    Inst I;     // caller pointers and shape; P filled by plan()
+    int tile[4];
+};
+
+// Copies 4-byte words of the batch header from the kernel arguments.
+constexpr int BLOB_WORDS = 768;
+struct Blob {
+    unsigned w[BLOB_WORDS];
+};
+
+__global__ __launch_bounds__(256) void k_blob(Blob b, unsigned *dst, int n) {
+    for (int i = threadIdx.x; i < n; i += 256) dst[i] = b.w[i];
+}
+
+// A planned call: per-instance regions, the header bytes, the host plan and
+// the device view.
+struct Plan {
+    std::vector<Layout> lay;
+    std::vector<size_t> region;
+    size_t inst_total = 0;
+    HeaderLayout hl;
+    size_t total = 0;
+    std::vector<unsigned char> hdr;
+    HostPlan hp;
+    BatchView bv;
+};
+
+static bool valid_tiles(const int *t, int H) {
+    if (t[0] < 0 || t[0] > 64) return false;
+    if (t[1] < 0 || t[1] > H) return false;
+    if (t[1] != 0 && t[1] != H && (t[1] < 16 || t[1] % 16 != 0)) return false;
+    return t[2] == 0 && t[3] == 0;
+}
+
+// Sizes only (ws == nullptr) or sizes, header bytes and device view.
+static void plan(std::vector<Spec> &spec, char *ws, int run, Plan &p) {
+    const int B = (int)spec.size();
+    p.lay.resize(B);
+    p.region.resize(B);
+    size_t o = 0;
+    long long sum_W = 0;
+    for (int b = 0; b < B; ++b) {
+        const Inst &I = spec[b].I;
+        p.lay[b] = make_layout(I.M, I.m, I.H, I.N);
+        p.region[b] = o;
+        o += p.lay[b].total;
+        sum_W += p.lay[b].W;
+    }
+    p.inst_total = o;
+    p.hl = header_layout(B);
+    p.total = o + p.hl.total;
+    if (!ws) return;
+
+    std::vector<Inst> tab(B);
+    std::vector<int> pt(B + 1), ref(B + 1), chunk(B + 1), tile(B + 1), order(B);
+    std::vector<long long> dom(B + 1), asc(B + 1);
+    pt[0] = ref[0] = chunk[0] = tile[0] = 0;
+    for (int b = 0; b < B; ++b) {
+        const Layout &L = p.lay[b];
+        Inst I = spec[b].I;
+        I.P = carve(L, ws + p.region[b]);
+        I.Mp = L.Mp;
+        I.W = L.W;
+        I.Hp = L.Hp;
+        I.ns = L.ns;
+        I.G = spec[b].tile[0] > 0 ? spec[b].tile[0] : DOM_G_DEFAULT;
+        I.R = spec[b].tile[1] > 0 ? spec[b].tile[1] : auto_slice(I.H, sum_W);
+        I.nslice = (I.H + I.R - 1) / I.R;
+        I.ntiles = (I.M + COMPACT_TILE - 1) / COMPACT_TILE;
+        tab[b] = I;
+        pt[b + 1] = pt[b] + (int)((I.M + PT_ALIGN - 1) / PT_ALIGN * PT_ALIGN);
+        ref[b + 1] = ref[b] + (int)((I.Hp + PT_ALIGN - 1) / PT_ALIGN * PT_ALIGN);
+        chunk[b + 1] = chunk[b] + I.W;
+        tile[b + 1] = tile[b] + I.ntiles;
+        order[b] = b;
+    }
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int c) { return tab[a].m < tab[c].m; });
+    HostPlan &hp = p.hp;
+    hp.B = B;
+    hp.npt = pt[B];
+    hp.nref = ref[B];
+    hp.nchunk = chunk[B];
+    hp.ntile = tile[B];
+    hp.ngroups = 0;
+    hp.max_W = 0;
+    dom[0] = asc[0] = 0;
+    for (int i = 0; i < B; ++i) {
+        const Inst &I = tab[order[i]];
+        dom[i + 1] = dom[i] + dominance_items(I.W, I.G);
+        asc[i + 1] = asc[i] + (long long)I.W * I.nslice;
+        if (I.W > hp.max_W) hp.max_W = I.W;
+        if (i == 0 || I.m != tab[order[i - 1]].m) {
+            hp.grp_m[hp.ngroups] = I.m;
+            hp.grp_start[hp.ngroups] = i;
+            ++hp.ngroups;
+        }
+    }
+    hp.grp_start[hp.ngroups] = B;
+    for (int g = 0; g <= hp.ngroups; ++g) {
+        hp.grp_dom[g] = dom[hp.grp_start[g]];
+        hp.grp_asc[g] = asc[hp.grp_start[g]];
+    }
+
+    // header bytes
+    const HeaderLayout &hl = p.hl;
+    p.hdr.assign(hl.total, 0);
+    unsigned char *h = p.hdr.data();
+    memcpy(h + hl.tab, tab.data(), (size_t)B * sizeof(Inst));
+    memcpy(h + hl.pt_pref, pt.data(), (size_t)(B + 1) * 4);
+    memcpy(h + hl.ref_pref, ref.data(), (size_t)(B + 1) * 4);
+    memcpy(h + hl.chunk_pref, chunk.data(), (size_t)(B + 1) * 4);
+    memcpy(h + hl.tile_pref, tile.data(), (size_t)(B + 1) * 4);
+    memcpy(h + hl.order, order.data(), (size_t)B * 4);
+    memcpy(h + hl.dom_pref, dom.data(), (size_t)(B + 1) * 8);
+    memcpy(h + hl.asc_pref, asc.data(), (size_t)(B + 1) * 8);
+
+    char *hd = ws + p.inst_total;
+    BatchView &bv = p.bv;
+    bv.tab = (const Inst *)(hd + hl.tab);
+    bv.pt_pref = (const int *)(hd + hl.pt_pref);
+    bv.ref_pref = (const int *)(hd + hl.ref_pref);
+    bv.chunk_pref = (const int *)(hd + hl.chunk_pref);
+    bv.tile_pref = (const int *)(hd + hl.tile_pref);
+    bv.order = (const int *)(hd + hl.order);
+    bv.dom_pref = (const long long *)(hd + hl.dom_pref);
+    bv.asc_pref = (const long long *)(hd + hl.asc_pref);
+    bv.ticket = (u64 *)(hd + hl.ticket);
+    bv.B = B;
+    bv.run = run;
+}
+
+// Enqueues the header copy, then the stages of `run`.
+static hipError_t enqueue(Plan &p, char *ws, hipStream_t s) {
+    unsigned *dst = (unsigned *)(ws + p.inst_total);
+    const unsigned *src = (const unsigned *)p.hdr.data();
+    const int words = (int)(p.hdr.size() / 4);
+    Blob blob;
+    for (int w0 = 0; w0 < words; w0 += BLOB_WORDS) {
+        const int n = std::min(BLOB_WORDS, words - w0);
+        memcpy(blob.w, src + w0, (size_t)n * 4);
+        NSGA3_LAUNCH("header", k_blob, dim3(1), dim3(256), 0, s, blob, dst + w0, n);
+    }
+    hipError_t e = launch_prepare(p.hp, p.bv, s);
+    const int run = p.bv.run;
+    if (e == hipSuccess && (run & RUN_ND)) e = launch_nd_sort(p.hp, p.bv, s);
+    if (e == hipSuccess && (run & RUN_NORM)) e = launch_normalize(p.hp, p.bv, s);
+    if (e == hipSuccess && (run & RUN_ASSOC)) e = launch_associate(p.hp, p.bv, s);
+    if (e == hipSuccess && (run & RUN_NICHE)) e = launch_niche(p.hp, p.bv, s);
+    return e;
+}
+
+static Spec blank_spec(int M, int m, int H, int N) {
+    Spec sp;
+    memset(&sp, 0, sizeof(sp));
+    sp.I.M = M;
+    sp.I.m = m;
+    sp.I.H = H;
+    sp.I.N = N;
+    sp.I.n_stop = N;
+    return sp;
+}
+
+static int check_ws(size_t need, const void *ws, size_t ws_bytes) {
     if (!ws || !aligned(ws, 256)) return NSGA3_EINVAL;
-    if (ws_bytes < L.total) return NSGA3_EWORKSPACE;
+    if (ws_bytes < need) return NSGA3_EWORKSPACE;
     return NSGA3_OK;
 }
 
-static int to_status(hipError_t e) { return e == hipSuccess ? NSGA3_OK : NSGA3_EHIP; }
+// Runs a one-instance call of the stages in `run`.
+static int run_single(Spec sp, void *ws, size_t ws_bytes, int run, hipStream_t s) {
+    std::vector<Spec> v(1, sp);
+    Plan p;
+    plan(v, nullptr, run, p);
+    const int rc = check_ws(p.total, ws, ws_bytes);
+    if (rc) return rc;
+    plan(v, (char *)ws, run, p);
+    return to_status(enqueue(p, (char *)ws, s));
+}
+
+static bool valid_instance(const nsga3_instance &q) {
+    return q.F && q.Z && q.selected && valid_shape(q.M, q.m, q.H, q.N) && aligned(q.F, 4) &&
+           aligned(q.Z, 4) && aligned(q.selected, 4) && (!q.rank || aligned(q.rank, 4)) &&
+           (!q.pi || aligned(q.pi, 4)) && (!q.dist || aligned(q.dist, 4)) &&
+           valid_tiles(q.tile, q.H);
+}
+
+static void specs_of(const nsga3_instance *inst, int B, std::vector<Spec> &v) {
+    v.resize(B);
+    for (int b = 0; b < B; ++b) {
+        const nsga3_instance &q = inst[b];
+        v[b] = blank_spec(q.M, q.m, q.H, q.N);
+        v[b].I.F = q.F;
+        v[b].I.Z = q.Z;
+        v[b].I.selected = q.selected;
+        v[b].I.rank = q.rank;
+        v[b].I.pi = q.pi;
+        v[b].I.dist = q.dist;
+        v[b].I.seed = q.seed;
+        for (int t = 0; t < 4; ++t) v[b].tile[t] = q.tile[t];
+    }
+}
+
+// Internal destinations of a selection: rank/pi/dist default to the
+// instance's region; front_info, Fn and the normalization outputs always do.
+static void place_select(Plan &p, std::vector<Spec> &v, char *ws) {
+    for (size_t b = 0; b < v.size(); ++b) {
+        const Ptrs P = carve(p.lay[b], ws + p.region[b]);
+        Inst &I = v[b].I;
+        if (!I.rank) I.rank = P.rank;
+        if (!I.pi) I.pi = P.pi;
+        if (!I.dist) I.dist = P.dist;
+        I.front_info = P.ctrl->front_info;
+        I.Fn = P.fn;
+        I.ideal = P.ctrl->ideal_out;
+        I.intercept = P.ctrl->icpt_out;
+        I.extreme = P.ctrl->ext_out;
+        I.degenerate = &P.ctrl->degen_out;
+    }
+}
+
+static int run_select(std::vector<Spec> &v, void *ws, size_t ws_bytes, hipStream_t s) {
+    Plan p;
+    plan(v, nullptr, RUN_SELECT, p);
+    const int rc = check_ws(p.total, ws, ws_bytes);
+    if (rc) return rc;
+    place_select(p, v, (char *)ws);
+    plan(v, (char *)ws, RUN_SELECT, p);
+    return to_status(enqueue(p, (char *)ws, s));
+}
+
+static int status_code(int bits) {
+    if (bits & ST_NONFINITE) return NSGA3_ENONFINITE;
+    if (bits & ST_BADREF) return NSGA3_EINVAL;
+    if (bits & ST_INTERNAL) return NSGA3_EINTERNAL;
+    return NSGA3_OK;
+}
 
 // ---------------------------------------------------------- instrumentation
 
@@ -161,7 +441,10 @@ extern "C" {
 
 size_t nsga3_workspace_bytes(int32_t M, int32_t m, int32_t H, int32_t N) {
     if (!valid_shape(M, m, H, N)) return 0;
-    return make_layout(M, m, H, N).total;
+    std::vector<Spec> v(1, blank_spec(M, m, H, N));
+    Plan p;
+    plan(v, nullptr, RUN_SELECT, p);
+    return p.total;
 }
 
 int nsga3_nd_sort(const float *F, int32_t M, int32_t m, int32_t n_stop, int32_t *rank,
@@ -169,12 +452,13 @@ int nsga3_nd_sort(const float *F, int32_t M, int32_t m, int32_t n_stop, int32_t 
     if (!F || !rank || !front_info || !valid_shape(M, m, 1, 1) || !aligned(F, 4) ||
         !aligned(rank, 4) || !aligned(front_info, 4))
         return NSGA3_EINVAL;
-    const Layout L = make_layout(M, m, 1, M);
-    int rc = check_ws(L, ws, ws_bytes);
-    if (rc) return rc;
     if (n_stop <= 0 || n_stop > M) n_stop = M;
-    const Ptrs P = carve(L, ws);
-    return to_status(launch_nd_sort(L, P, F, n_stop, rank, front_info, true, (hipStream_t)stream));
+    Spec sp = blank_spec(M, m, 1, M);
+    sp.I.F = F;
+    sp.I.rank = rank;
+    sp.I.front_info = front_info;
+    sp.I.n_stop = n_stop;
+    return run_single(sp, ws, ws_bytes, RUN_ND, (hipStream_t)stream);
 }
 
 int nsga3_normalize(const float *F, const int32_t *rank, const int32_t *front_info, int32_t M,
@@ -183,12 +467,16 @@ int nsga3_normalize(const float *F, const int32_t *rank, const int32_t *front_in
     if (!F || !rank || !front_info || !Fn || !ideal || !intercept || !extreme || !degenerate ||
         !valid_shape(M, m, 1, 1) || !aligned(F, 4) || !aligned(Fn, 4) || !aligned(intercept, 8))
         return NSGA3_EINVAL;
-    const Layout L = make_layout(M, m, 1, M);
-    int rc = check_ws(L, ws, ws_bytes);
-    if (rc) return rc;
-    const Ptrs P = carve(L, ws);
-    return to_status(launch_normalize(L, P, F, rank, front_info, Fn, ideal, intercept, extreme,
-                                      degenerate, true, (hipStream_t)stream));
+    Spec sp = blank_spec(M, m, 1, M);
+    sp.I.F = F;
+    sp.I.rank = (int *)rank;              // read only in this call
+    sp.I.front_info = (int *)front_info;  // read only in this call
+    sp.I.Fn = Fn;
+    sp.I.ideal = ideal;
+    sp.I.intercept = intercept;
+    sp.I.extreme = extreme;
+    sp.I.degenerate = degenerate;
+    return run_single(sp, ws, ws_bytes, RUN_NORM, (hipStream_t)stream);
 }
 
 int nsga3_associate(const float *Fn, const int32_t *rank, const int32_t *front_info, int32_t M,
@@ -197,12 +485,14 @@ int nsga3_associate(const float *Fn, const int32_t *rank, const int32_t *front_i
     if (!Fn || !rank || !front_info || !Z || !pi || !dist || !valid_shape(M, m, H, 1) ||
         !aligned(Fn, 4) || !aligned(Z, 4))
         return NSGA3_EINVAL;
-    const Layout L = make_layout(M, m, H, M);
-    int rc = check_ws(L, ws, ws_bytes);
-    if (rc) return rc;
-    const Ptrs P = carve(L, ws);
-    return to_status(
-        launch_associate(L, P, Fn, rank, front_info, Z, pi, dist, true, (hipStream_t)stream));
+    Spec sp = blank_spec(M, m, H, M);
+    sp.I.Fn = (float *)Fn;                // read only in this call
+    sp.I.rank = (int *)rank;
+    sp.I.front_info = (int *)front_info;
+    sp.I.Z = Z;
+    sp.I.pi = pi;
+    sp.I.dist = dist;
+    return run_single(sp, ws, ws_bytes, RUN_ASSOC, (hipStream_t)stream);
 }
 
 int nsga3_niche(const int32_t *rank, const int32_t *front_info, const int32_t *pi,
@@ -210,35 +500,59 @@ int nsga3_niche(const int32_t *rank, const int32_t *front_info, const int32_t *p
                 int32_t *selected, void *ws, size_t ws_bytes, void *stream) {
     if (!rank || !front_info || !pi || !dist || !selected || !valid_shape(M, 2, H, N))
         return NSGA3_EINVAL;
-    const Layout L = make_layout(M, 2, H, N);
-    int rc = check_ws(L, ws, ws_bytes);
-    if (rc) return rc;
-    const Ptrs P = carve(L, ws);
-    return to_status(
-        launch_niche(L, P, rank, front_info, pi, dist, seed, selected, true, (hipStream_t)stream));
+    Spec sp = blank_spec(M, 2, H, N);
+    sp.I.rank = (int *)rank;              // read only in this call
+    sp.I.front_info = (int *)front_info;
+    sp.I.pi = (int *)pi;
+    sp.I.dist = (float *)dist;
+    sp.I.seed = seed;
+    sp.I.selected = selected;
+    return run_single(sp, ws, ws_bytes, RUN_NICHE, (hipStream_t)stream);
 }
 
 int nsga3_select(const float *F, int32_t M, int32_t m, const float *Z, int32_t H, int32_t N,
                  uint64_t seed, int32_t *selected, int32_t *rank_out, int32_t *pi_out,
                  float *dist_out, void *ws, size_t ws_bytes, void *stream) {
-    if (!F || !Z || !selected || !valid_shape(M, m, H, N) || !aligned(F, 4) || !aligned(Z, 4))
-        return NSGA3_EINVAL;
-    const Layout L = make_layout(M, m, H, N);
-    int rc = check_ws(L, ws, ws_bytes);
-    if (rc) return rc;
-    const Ptrs P = carve(L, ws);
-    hipStream_t s = (hipStream_t)stream;
-    int *rank = rank_out ? rank_out : P.rank;
-    int *pi = pi_out ? pi_out : P.pi;
-    float *dist = dist_out ? dist_out : P.dist;
-    int *fi = P.ctrl->front_info;
-    hipError_t e = launch_nd_sort(L, P, F, N, rank, fi, true, s);
-    if (e == hipSuccess)
-        e = launch_normalize(L, P, F, rank, fi, P.fn, P.ctrl->ideal_out, P.ctrl->icpt_out,
-                             P.ctrl->ext_out, &P.ctrl->degen_out, false, s);
-    if (e == hipSuccess) e = launch_associate(L, P, P.fn, rank, fi, Z, pi, dist, false, s);
-    if (e == hipSuccess) e = launch_niche(L, P, rank, fi, pi, dist, seed, selected, false, s);
-    return to_status(e);
+    nsga3_instance q;
+    memset(&q, 0, sizeof(q));
+    q.F = F;
+    q.Z = Z;
+    q.selected = selected;
+    q.rank = rank_out;
+    q.pi = pi_out;
+    q.dist = dist_out;
+    q.M = M;
+    q.m = m;
+    q.H = H;
+    q.N = N;
+    q.seed = seed;
+    if (!valid_instance(q)) return NSGA3_EINVAL;
+    std::vector<Spec> v;
+    specs_of(&q, 1, v);
+    return run_select(v, ws, ws_bytes, (hipStream_t)stream);
+}
+
+size_t nsga3_batched_workspace_bytes(const nsga3_instance *inst, int32_t B) {
+    if (!inst || B < 1 || B > NSGA3_MAX_BATCH) return 0;
+    for (int b = 0; b < B; ++b)
+        if (!valid_shape(inst[b].M, inst[b].m, inst[b].H, inst[b].N) ||
+            !valid_tiles(inst[b].tile, inst[b].H))
+            return 0;
+    std::vector<Spec> v;
+    specs_of(inst, B, v);
+    Plan p;
+    plan(v, nullptr, RUN_SELECT, p);
+    return p.total;
+}
+
+int nsga3_select_batched(const nsga3_instance *inst, int32_t B, void *ws, size_t ws_bytes,
+                         void *stream) {
+    if (!inst || B < 1 || B > NSGA3_MAX_BATCH) return NSGA3_EINVAL;
+    for (int b = 0; b < B; ++b)
+        if (!valid_instance(inst[b])) return NSGA3_EINVAL;
+    std::vector<Spec> v;
+    specs_of(inst, B, v);
+    return run_select(v, ws, ws_bytes, (hipStream_t)stream);
 }
 
 int nsga3_read_status(const void *ws, void *stream, int32_t *status) {
@@ -249,10 +563,29 @@ int nsga3_read_status(const void *ws, void *stream, int32_t *status) {
     if (hipMemcpyAsync(&bits, &ctrl->status, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess)
         return NSGA3_EHIP;
     if (hipStreamSynchronize(s) != hipSuccess) return NSGA3_EHIP;
-    if (bits & ST_NONFINITE) *status = NSGA3_ENONFINITE;
-    else if (bits & ST_BADREF) *status = NSGA3_EINVAL;
-    else if (bits & ST_INTERNAL) *status = NSGA3_EINTERNAL;
-    else *status = NSGA3_OK;
+    *status = status_code(bits);
+    return NSGA3_OK;
+}
+
+int nsga3_read_status_batched(const nsga3_instance *inst, int32_t B, const void *ws,
+                              void *stream, int32_t *status) {
+    if (!inst || !ws || !status || B < 1 || B > NSGA3_MAX_BATCH) return NSGA3_EINVAL;
+    for (int b = 0; b < B; ++b)
+        if (!valid_shape(inst[b].M, inst[b].m, inst[b].H, inst[b].N)) return NSGA3_EINVAL;
+    std::vector<Spec> v;
+    specs_of(inst, B, v);
+    Plan p;
+    plan(v, nullptr, RUN_SELECT, p);
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<int> bits(B, 0);
+    for (int b = 0; b < B; ++b) {
+        const Ctrl *ctrl = (const Ctrl *)((const char *)ws + p.region[b]);
+        if (hipMemcpyAsync(&bits[b], &ctrl->status, sizeof(int), hipMemcpyDeviceToHost, s) !=
+            hipSuccess)
+            return NSGA3_EHIP;
+    }
+    if (hipStreamSynchronize(s) != hipSuccess) return NSGA3_EHIP;
+    for (int b = 0; b < B; ++b) status[b] = status_code(bits[b]);
     return NSGA3_OK;
 }
 

@@ -1,73 +1,109 @@
 // Non-dominated sorting (paper Sec. II-C; Algorithm 1 "Non-dominated-sort")
-// as a bit-packed dominance matrix followed by front peeling.
+// as a bit-packed dominance matrix followed by front peeling, for a batch of
+// independent instances.
 //
 // Dominance matrix layout ("word-major"): mask[w * Mp + j] is a 64-bit word
 // whose bit b is set iff point 64*w + b dominates point j. A wave of 64
 // consecutive j therefore reads or writes 512 contiguous bytes.
 //
 // Kernels:
-//   k_nd_init    reset of the control block
-//   k_nd_prep    tile-major copy of the objectives (64 points x m coordinates
-//                contiguous per tile, +inf padding), finiteness check,
-//                zeroed dominator counts, alive set of front 0
-//   k_dominance  triangle of 64x64 tiles; per tile both directions from one
-//                set of 2m compares per pair; fused dominator counts
-//   k_peel       fronts peeled by a ticketed work queue: items of front k
-//                wait until every item of front k-1 completed
+//   k_init       per instance: control block, peel counters, front_info
+//   k_prep       points: tile-major objective copy (+inf padding), finiteness,
+//                dominator counts, ranks, alive set of front 0, niche flags;
+//                references: unit directions and their check, niche counters
+//   k_dominance  triangle of 64x64 tiles; both directions from one set of 2m
+//                compares per pair; fused dominator counts
+//   k_peel       fronts of every instance, persistent over all their chunks
 #include <utility>
 
 #include "nsga3_internal.h"
 
 namespace nsga3 {
 
-// front-peeling ring of completion counters: 3 slots of 32 shard counters and
-// one top word, each on its own 256-byte line
-constexpr int PEEL_SHARDS = 32;
-constexpr int PEEL_STRIDE = 32;                       // u64 words between counters (256 B)
-constexpr int PEEL_SLOT = (PEEL_SHARDS + 1) * PEEL_STRIDE;
-constexpr int PEEL_OWN_CAP = 2048;
-constexpr int ALIVE_PAD = 16;  // u64 words per alive word (one 128-byte line)
-
-__global__ void k_nd_init(Ctrl *ctrl, u64 *ring, int *front_info, int n_stop, bool reset_status) {
-    for (int i = threadIdx.x; i < 3 * PEEL_SLOT; i += blockDim.x) ring[i] = 0;
-    if (threadIdx.x == 0) {
-        if (reset_status) ctrl->status = 0;
-        // a defined value even if the peel stops on an internal error
-        front_info[0] = 0;
-        front_info[1] = 0;
-        front_info[2] = n_stop;
-        front_info[3] = 0;
-        ctrl->ticket = 0;
-        ctrl->completed = 0;
-        ctrl->ranked = 0;
-        ctrl->finished = 0;
-    }
+long long dominance_items(int W, int G_) {
+    const long long G = G_, q = W / G, s = W % G;
+    return (long long)W + G * q * (q - 1) / 2 + q * s;
 }
 
-__global__ __launch_bounds__(256) void k_nd_prep(const float *__restrict__ F, int M, int m, int Mp,
-                                                  float *__restrict__ ft, int *__restrict__ nd,
-                                                  int *__restrict__ rank, u64 *__restrict__ alive0,
-                                                  Ctrl *ctrl) {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    bool bad = false;
-    if (j < Mp) {
-        for (int k = 0; k < m; ++k) {
-            float v = INFINITY;
-            if (j < M) {
-                v = F[(size_t)j * m + k];
-                bad |= !isfinite(v);
-            }
-            ft[((size_t)(j >> 6) * m + k) * 64 + (j & 63)] = v;
-        }
-        nd[j] = 0;
-        if (j < M) rank[j] = NSGA3_UNRANKED;
-        if ((j & 63) == 0) {
-            int valid = M - j;
-            alive0[(size_t)(j >> 6) * ALIVE_PAD] =
-                valid >= 64 ? ~0ull : (valid <= 0 ? 0ull : ((1ull << valid) - 1));
+__global__ __launch_bounds__(256) void k_init(BatchView bv) {
+    const Inst &I = bv.tab[blockIdx.x];
+    Ctrl *ctrl = I.P.ctrl;
+    const int t = threadIdx.x;
+    if (t == 0) {
+        ctrl->status = 0;
+        ctrl->list_count = 0;
+        if (bv.run & RUN_ND) {
+            // a defined value even if the peel stops on an internal error
+            I.front_info[0] = 0;
+            I.front_info[1] = 0;
+            I.front_info[2] = I.n_stop;
+            I.front_info[3] = 0;
         }
     }
-    if (ballot(bad) != 0 && lane_id() == 0) atomicOr(&ctrl->status, ST_NONFINITE);
+    if (blockIdx.x == 0 && t == 0) *bv.ticket = 0;
+    if (t < NSGA3_MAX_OBJECTIVES) {
+        ctrl->zmin_enc[t] = 0xffffffffu;
+        ctrl->fmax_enc[t] = 0u;
+        ctrl->ext_key[t] = ~0ull;
+    }
+    if (bv.run & RUN_ND)
+        for (int i = t; i < 3 * PEEL_SLOT; i += blockDim.x) I.P.facc[i] = 0;
+}
+
+// Grid: [all instances' padded points][all instances' padded references].
+__global__ __launch_bounds__(256) void k_prep(BatchView bv, int npt) {
+    const bool points = (int)(blockIdx.x * blockDim.x) < npt;
+    if (points) {
+        const Local L = locate(bv.pt_pref, bv.B);
+        const Inst &I = bv.tab[L.b];
+        const int j = L.i, M = I.M, m = I.m, Mp = I.Mp;
+        bool bad = false;
+        if (j < Mp && (bv.run & RUN_ND)) {
+            for (int k = 0; k < m; ++k) {
+                float v = INFINITY;
+                if (j < M) {
+                    v = I.F[(size_t)j * m + k];
+                    bad |= !isfinite(v);
+                }
+                I.P.ft[((size_t)(j >> 6) * m + k) * 64 + (j & 63)] = v;
+            }
+            I.P.nd[j] = 0;
+            if (j < M) I.rank[j] = NSGA3_UNRANKED;
+            if ((j & 63) == 0) {
+                const int valid = M - j;
+                I.P.alive[(size_t)(j >> 6) * ALIVE_PAD] =
+                    valid >= 64 ? ~0ull : (valid <= 0 ? 0ull : ((1ull << valid) - 1));
+            }
+        }
+        if (j < M && (bv.run & RUN_NICHE)) I.P.picked[j] = 0;
+        if (ballot(bad) != 0 && lane_id() == 0) atomicOr(&I.P.ctrl->status, ST_NONFINITE);
+    } else {
+        const int base = uniform((int)(blockIdx.x * blockDim.x)) - npt;
+        const int b = uniform(find_range(bv.ref_pref, bv.B, base));
+        const Inst &I = bv.tab[b];
+        const int t = base - bv.ref_pref[b] + (int)threadIdx.x;
+        const int H = I.H, Hp = I.Hp, m = I.m;
+        bool bad = false;
+        if (t < Hp && (bv.run & RUN_ASSOC)) {
+            // unit reference directions; padding repeats the last real one
+            const int j = t < H ? t : H - 1;
+            float s = 0.0f;
+            for (int k = 0; k < m; ++k) {
+                const float v = I.Z[(size_t)j * m + k];
+                bad |= !(v >= 0.0f) || !isfinite(v);
+                s = fmaf(v, v, s);
+            }
+            bad |= !(s > 0.0f);
+            const float inv = bad ? 0.0f : 1.0f / sqrtf(s);
+            for (int k = 0; k < m; ++k) I.P.wn[(size_t)k * Hp + t] = I.Z[(size_t)j * m + k] * inv;
+        }
+        if (t < H && (bv.run & RUN_NICHE)) {
+            I.P.rho[t] = 0;
+            I.P.cnt[t] = 0;
+            I.P.fill[t] = 0;
+        }
+        if (ballot(bad) != 0 && lane_id() == 0) atomicOr(&I.P.ctrl->status, ST_BADREF);
+    }
 }
 
 // (a << 1) | bit(lane) for every lane, with the bits taken from a wave mask:
@@ -86,10 +122,8 @@ __device__ __forceinline__ unsigned write_lane(unsigned old, unsigned v) {
     return old;
 }
 
-// Number of work items for block rows 0..jb-1 when row jb holds floor(jb/G)+1
-// items of up to G column tiles each.
 __device__ __forceinline__ long long items_before(long long jb, long long G) {
-    long long q = jb / G, s = jb % G;
+    const long long q = jb / G, s = jb % G;
     return jb + G * q * (q - 1) / 2 + q * s;
 }
 
@@ -127,22 +161,29 @@ __device__ __forceinline__ void dom_tile(std::integer_sequence<int, Is...>,
     (dom_step<MO, 63 - Is>(fi, fj, a_lo, a_hi, b_lo, b_hi), ...);
 }
 
-// One wave per work item: the 64 points of block row jb sit in the lanes
-// (as the dominated side j); the item sweeps up to G column blocks ib <= jb,
-// reading the column points through the scalar cache.
+// One wave per work item of the instances with m = MO (the group order[gs ..
+// gs + gn)): the 64 points of block row jb sit in the lanes (as the dominated
+// side j); the item sweeps up to G column blocks ib <= jb, reading the
+// column points through the scalar cache.
 template <int MO>
-__global__ __launch_bounds__(256) void k_dominance(const float *__restrict__ ft, int Mp, int W,
-                                                    int G, long long n_items,
-                                                    u64 *__restrict__ mask,
-                                                    int *__restrict__ nd) {
+__global__ __launch_bounds__(256) void k_dominance(BatchView bv, int gs, int gn,
+                                                    long long item0, long long n_items) {
     const int lane = lane_id();
-    const long long item = uniform((long long)blockIdx.x * 4 + (threadIdx.x >> 6));
-    if (item >= n_items) return;
-    // locate the block row: largest jb with items_before(jb) <= item
-    int lo = 0, hi = W;  // items_before(lo) <= item < items_before(hi)
+    const long long gitem = uniform(item0 + (long long)blockIdx.x * 4 + (threadIdx.x >> 6));
+    if (gitem >= item0 + n_items) return;
+    const int gi = uniform(find_range(bv.dom_pref + gs, gn, gitem));
+    const Inst &I = bv.tab[bv.order[gs + gi]];
+    const long long item = gitem - bv.dom_pref[gs + gi];
+    const int W = I.W, Mp = I.Mp, G = I.G;
+    const float *__restrict__ ft = I.P.ft;
+    u64 *__restrict__ mask = I.P.mask;
+    int *__restrict__ nd = I.P.nd;
+    // block row: largest jb with items_before(jb) <= item
+    int lo = 0, hi = W;
     while (hi - lo > 1) {
-        int mid = (lo + hi) >> 1;
-        if (items_before(mid, G) <= item) lo = mid; else hi = mid;
+        const int mid = (lo + hi) >> 1;
+        if (items_before(mid, G) <= item) lo = mid;
+        else hi = mid;
     }
     const int jb = lo;
     const int g = (int)(item - items_before(jb, G));
@@ -172,74 +213,66 @@ __global__ __launch_bounds__(256) void k_dominance(const float *__restrict__ ft,
     if (cnt_j) atomicAdd(&nd[jglob], cnt_j);
 }
 
-constexpr int PEEL_WAVES = 8;
-constexpr int PEEL_UNROLL = 12;
-
-__device__ __forceinline__ u64 load_relaxed(const u64 *p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ int load_relaxed(const int *p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void store_relaxed(u64 *p, u64 v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void store_relaxed(int *p, int v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
 // Front peeling.
 //
-// Chunk c holds the 64 points 64c .. 64c+63. Front 0 is {j : no dominator}
-// (fused counts of the dominance kernel). A point j alive at front k > 0
-// belongs to it iff no alive point dominates it. Fronts after the first are
-// found with witnesses: every alive point keeps one alive dominator (its
-// witness) and is re-examined only once its witness has been ranked. The
-// re-examination resumes the scan of j's row at the witness's word: the
-// words before it held no alive dominator when they were scanned, and the
-// alive set only shrinks. Over the whole peel each row is read about once.
-// The scans read a row-major copy of the dominance matrix (row j = the W
+// Chunk c of an instance holds its 64 points 64c .. 64c+63. Front 0 is
+// {j : no dominator} (fused counts of the dominance kernel). A point j alive
+// at front k > 0 belongs to it iff no alive point dominates it. Fronts after
+// the first are found with witnesses: every alive point keeps one alive
+// dominator (its witness) and is re-examined only once its witness has been
+// ranked. The re-examination resumes the scan of j's row at the witness's
+// word: the words before it held no alive dominator when they were scanned,
+// and the alive set only shrinks. Over the whole peel each row is read about
+// once. The scans read a row-major copy of the dominance matrix (row j = the W
 // words of point j's dominators), which each workgroup writes for its own
-// chunks when front 1 starts; when front 0 already fills N it is never built.
-// The alive sets of consecutive fronts alternate between two bitsets.
+// chunks when their instance starts front 1; an instance whose front 0
+// already fills N never builds it. The peel of an instance stops once its
+// ranked fronts hold n_stop points.
 //
-// Scheduling. While ranking front 0, workgroups claim chunks from a ticket
-// counter until every chunk is claimed; a workgroup then owns its chunks for
-// all later fronts. Only running workgroups claim, and no workgroup waits
-// before all chunks are claimed and ranked for front 0, so every wait ends.
-// A workgroup records at most PEEL_OWN_CAP chunks; if every running
-// workgroup were full the front-0 wait would time out into an error status.
+// Scheduling. While ranking front 0, workgroups claim chunks (of any
+// instance) from a ticket counter until every chunk is claimed; a workgroup
+// then owns its chunks for all later fronts and processes them front by
+// front. Only running workgroups claim, and no workgroup waits before all
+// chunks are claimed and ranked for front 0; later waits are for lower fronts
+// of chunks owned by running workgroups, so every wait ends. A workgroup
+// records at most PEEL_OWN_CAP chunks; if every running workgroup were full
+// the front-0 wait would time out into an error status.
 //
 // Completion. Per front, chunk c adds (points ranked << 32) + 1 to shard
-// counter c % PEEL_SHARDS (a fire-and-forget atomic); a waiting workgroup
-// reads the 32 shards with one wave and sums them. Counters live in a ring of
-// three front slots; the slot of front k + 1 is cleared while front k is
-// processed (after front k - 1 completed, nobody reads it).
+// counter c % PEEL_SHARDS of its instance (a fire-and-forget atomic); a
+// waiting workgroup reads the 32 shards with one wave and sums them. Counters
+// live in a ring of three front slots per instance; the slot of front k + 1
+// is cleared while front k is processed (after front k - 1 completed, nobody
+// reads it).
 //
 // Memory ordering. Alive words and counters are written with agent-scope
 // atomic stores, which go to the coherent level; each chunk waits for its
-// stores before its counter add. A workgroup polls the counters with relaxed
-// atomic loads, and once a front is complete issues one agent-scope acquire
-// fence, after which ordinary cached loads see the published alive words.
-// The row-major copy and the witnesses of a chunk are touched only by its
-// owner. No L2 write-back is needed on this path.
+// stores before its counter add. Waiters poll the counters with relaxed
+// atomic loads. Alive words are then read with ordinary cached loads: the
+// word of each chunk sits alone on a 128-byte line of a per-front slot, so
+// no line is written by two workgroups and none is cached before it is read;
+// slots are reused only after `ns` fronts, and then an agent-scope acquire
+// drops stale copies. The row-major copy and the witnesses of a chunk are
+// touched only by its owner.
 //
 // Control flow is wave-uniform around every workgroup barrier: wave 0 makes
 // the scheduling decisions with all its lanes and shares them through LDS.
+constexpr int PEEL_WAVES = 8;
+constexpr int PEEL_OWN_CAP = 1024;
 constexpr int PEEL_LDS_ALIVE = 2048;  // alive words staged in LDS (M <= 131072)
 
 __device__ __forceinline__ u64 *peel_slot(u64 *ring, int k) { return ring + (size_t)(k % 3) * PEEL_SLOT; }
 
-// Alive bitset of front k: slot k % ns of the alive ring; the word of chunk c
-// sits alone on a 128-byte line (ALIVE_PAD words), so no two workgroups ever
-// write the same line and a slot is never cached before it is read.
+// Alive bitset of front k: slot k % ns of the alive ring.
 __device__ __forceinline__ u64 *alive_slot(u64 *aring, int W, int ns, int k) {
     return aring + (size_t)(k % ns) * W * ALIVE_PAD;
 }
 
 struct PeelShared {
-    int own[PEEL_OWN_CAP];
-    union {                    // the transpose (front 1 start) and the scans never overlap
+    int own_b[PEEL_OWN_CAP];    // instance of each owned chunk
+    int own_c[PEEL_OWN_CAP];    // chunk within its instance
+    int own_cum[PEEL_OWN_CAP];  // points in the instance's fronts seen so far (-1: done)
+    union {                     // the transpose (front 1 start) and the scans never overlap
         u64 alive[PEEL_LDS_ALIVE];
         u64 tile[64][65];
     };
@@ -251,10 +284,12 @@ struct PeelShared {
 
 // Row-major copy of chunk c's rows: rowm[j][w] = mask[w][j], through a
 // padded 64 x 64-word LDS tile (coalesced reads and writes).
-__device__ void peel_transpose(const u64 *__restrict__ mask, u64 *__restrict__ rowm, int *wit,
-                               int Mp, int W, int c, PeelShared &sh) {
+__device__ void peel_transpose(const Inst &I, int c, PeelShared &sh) {
     const int lane = lane_id();
     const int wv = uniform((int)(threadIdx.x >> 6));
+    const int W = I.W, Mp = I.Mp;
+    const u64 *__restrict__ mask = I.P.mask;
+    u64 *__restrict__ rowm = I.P.rowm;
     for (int w0 = 0; w0 < W; w0 += 64) {
 #pragma unroll
         for (int q = 0; q < 64 / PEEL_WAVES; ++q) {
@@ -271,40 +306,31 @@ __device__ void peel_transpose(const u64 *__restrict__ mask, u64 *__restrict__ r
         }
         __syncthreads();
     }
-    if (threadIdx.x < 64) wit[c * 64 + lane] = -1;
+    if (wv == 0) I.P.wit[c * 64 + lane] = -1;
 }
 
 // Ranks the points of chunk c that are alive at front k and have no alive
-// dominator; publishes the chunk's result. All 16 waves take part.
-#ifdef NSGA3_PEEL_TRACE
-__device__ u64 *g_trace;
-#define PEEL_MARK(i)                                                                       \
-    if (k == 2 && threadIdx.x == 0)                                                       \
-        g_trace[2 * 16 * W + 8 * c + (i)] = __builtin_amdgcn_s_memrealtime();
-#else
-#define PEEL_MARK(i)
-#endif
-__device__ void peel_chunk(const int *__restrict__ nd, const u64 *__restrict__ rowm, int *wit,
-                           int W, int ns, int k, int c, u64 *alive, int *rank, u64 *ring,
-                           PeelShared &sh) {
+// dominator; publishes the chunk's result. All waves take part.
+__device__ void peel_chunk(const Inst &I, int k, int c, PeelShared &sh) {
     const int lane = lane_id();
     const int wv = uniform((int)(threadIdx.x >> 6));
-    const u64 *alive_k = alive_slot(alive, W, ns, k);
-    u64 *alive_n = alive_slot(alive, W, ns, k + 1);
+    const int W = I.W, ns = I.ns;
+    const u64 *alive_k = alive_slot(I.P.alive, W, ns, k);
+    u64 *alive_n = alive_slot(I.P.alive, W, ns, k + 1);
     const u64 aw = uniform(alive_k[(size_t)c * ALIVE_PAD]);
     const int j = c * 64 + lane;
     u64 newly;
     if (k == 0) {
-        newly = aw & ballot(nd[j] == 0);
+        newly = aw & ballot(I.P.nd[j] == 0);
     } else {
         const bool staged = W <= PEEL_LDS_ALIVE;
-        PEEL_MARK(0)
+        const u64 *__restrict__ rowm = I.P.rowm;
+        int *wit = I.P.wit;
         __syncthreads();  // the previous chunk is done with the shared words
         if (staged && aw != 0)
             for (int w = threadIdx.x; w < W; w += blockDim.x) sh.alive[w] = alive_k[(size_t)w * ALIVE_PAD];
         if (wv == 0) sh.newly = 0;
         __syncthreads();
-        PEEL_MARK(1)
         // points whose witness is still alive stay dominated
         if (wv == 0) {
             bool need = false;
@@ -320,9 +346,7 @@ __device__ void peel_chunk(const int *__restrict__ nd, const u64 *__restrict__ r
             sh.need = ballot(need);
         }
         __syncthreads();
-        PEEL_MARK(2)
         const u64 need = uniform(sh.need);
-        const int nneed = __popcll(need);
         // wave wv re-examines the needing points wv, wv + PEEL_WAVES, ... (lane
         // order); the first 64-word round of all of them is issued at once
         constexpr int PER = 64 / PEEL_WAVES;
@@ -373,7 +397,7 @@ __device__ void peel_chunk(const int *__restrict__ nd, const u64 *__restrict__ r
                     const u64 xl = ((u64)hi << 32) | lo;
                     const int cand = (pos + L) * 64 + lane;
                     const bool has = (xl >> lane) & 1ull;
-                    const u64 key = has ? (((u64)(unsigned)nd[cand] << 32) | (unsigned)(~cand)) : 0ull;
+                    const u64 key = has ? (((u64)(unsigned)I.P.nd[cand] << 32) | (unsigned)(~cand)) : 0ull;
                     const u64 best = wave_max_u64(key);
                     found = (int)~(unsigned)(best & 0xffffffffull);
                     break;
@@ -388,57 +412,43 @@ __device__ void peel_chunk(const int *__restrict__ nd, const u64 *__restrict__ r
             if (found < 0 && lane == 0) atomicOr(&sh.newly, 1ull << p);
         }
         __syncthreads();
-        PEEL_MARK(3)
         newly = aw & uniform(sh.newly);
     }
     if (wv == 0) {
         store_relaxed(&alive_n[(size_t)c * ALIVE_PAD], aw & ~newly);
         __builtin_amdgcn_s_waitcnt(0);
-        u64 *slot = peel_slot(ring, k);
+        u64 *slot = peel_slot(I.P.facc, k);
         const u64 add = ((u64)__popcll(newly) << 32) | 1ull;
         __hip_atomic_fetch_add(&slot[(c % PEEL_SHARDS) * PEEL_STRIDE], lane == 0 ? add : 0ull,
                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if ((newly >> lane) & 1ull) rank[j] = k;  // read only by later kernels
-#ifdef NSGA3_PEEL_TRACE
-        if (k == 2 && lane == 0) {
-            g_trace[2 * 16 * W + 8 * c + 4] = __builtin_amdgcn_s_memrealtime();
-            g_trace[2 * 16 * W + 8 * c + 5] = blockIdx.x;
-            g_trace[2 * 16 * W + 8 * c + 6] = __popcll(uniform(sh.need));
-        }
-#endif
+        if ((newly >> lane) & 1ull) I.rank[j] = k;  // read only by later kernels
     }
 }
 
-__global__ __launch_bounds__(64 * PEEL_WAVES) void k_peel(const u64 *__restrict__ mask,
-                                                const int *__restrict__ nd, int M, int Mp, int W,
-                                                int n_stop, int ns, u64 *alive, int *rank,
-                                                u64 *ring, u64 *rowm, int *wit, Ctrl *ctrl,
-                                                int *front_info
-#ifdef NSGA3_PEEL_TRACE
-                                                , u64 *trace
-#endif
-                                                ) {
+__global__ __launch_bounds__(64 * PEEL_WAVES) void k_peel(BatchView bv, int nchunk) {
     __shared__ PeelShared sh;
-#ifdef NSGA3_PEEL_TRACE
-    g_trace = trace;
-#endif
-    // drop cached lines of alive slots read by an earlier call on this workspace
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     const int lane = lane_id();
     const int wv = uniform((int)(threadIdx.x >> 6));
     const u64 one = lane == 0 ? 1ull : 0ull;
+    // drop cached lines of alive slots read by an earlier call on these workspaces
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
 
     // front 0: claim and rank chunks until all are claimed
     int nown = 0;
     for (;;) {
-        if (wv == 0) sh.val = uniform(atomicAdd(&ctrl->ticket, one));
+        if (wv == 0) sh.val = uniform(atomicAdd(bv.ticket, one));
         __syncthreads();
         const u64 t = uniform(sh.val);
         __syncthreads();
-        if (t >= (u64)W) break;
-        const int c = (int)t;
-        peel_chunk(nd, rowm, wit, W, ns, 0, c, alive, rank, ring, sh);
-        if (wv == 0) sh.own[nown] = c;
+        if (t >= (u64)nchunk) break;
+        const int b = uniform(find_range(bv.chunk_pref, bv.B, (int)t));
+        const int c = (int)t - bv.chunk_pref[b];
+        peel_chunk(bv.tab[b], 0, c, sh);
+        if (wv == 0) {
+            sh.own_b[nown] = b;
+            sh.own_c[nown] = c;
+            sh.own_cum[nown] = 0;
+        }
         ++nown;
         if (nown == PEEL_OWN_CAP) break;
     }
@@ -447,94 +457,94 @@ __global__ __launch_bounds__(64 * PEEL_WAVES) void k_peel(const u64 *__restrict_
     // chunks report the front fill
     if (nown == 0) return;
 
-    int cum = 0;
     for (int k = 1;; ++k) {
-        // wait for front k - 1
-        if (wv == 0) {
-            const u64 *slot = peel_slot(ring, k - 1);
-            u64 v = 0;
-            int ok = 1;
-            for (unsigned polls = 0;; ++polls) {
-                // lanes 0..31 read one shard each; the wave sums (count, size)
-                u64 part = lane < PEEL_SHARDS ? load_relaxed(&slot[lane * PEEL_STRIDE]) : 0ull;
-                v = uniform(wave_sum(part));
-                if ((unsigned)(v & 0xffffffffull) >= (unsigned)W) break;
-                if (polls == (1u << 26)) { ok = 0; break; }
-                __builtin_amdgcn_s_sleep(2);
-            }
-            sh.val = v;
-            sh.flag = ok;
-        }
-        __syncthreads();
-        const u64 v = uniform(sh.val);
-        const int ok = uniform(sh.flag);
-        // alive slots are reused only after ns fronts: then cached copies of the
-        // slot read ns fronts ago must be dropped before it is read again
-        if (k + 1 >= ns) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        __syncthreads();
-        const int size = (int)(v >> 32);
-        const int prev = cum;
-        cum += size;
-        if (!ok || cum >= n_stop || size == 0) {
-            if (wv == 0) {
-                if (!ok || size == 0) atomicOr(&ctrl->status, ST_INTERNAL);
-                front_info[0] = k - 1;
-                front_info[1] = prev;
-                front_info[2] = n_stop - prev;
-                front_info[3] = k;
-            }
-            break;
-        }
-        // clear the counters of front k + 1 (last read while waiting for front k - 2);
-        // this workgroup's own front-k publish, which front k + 1 waits for, is
-        // ordered after these stores
-        if (wv == 0 && lane <= PEEL_SHARDS) store_relaxed(&peel_slot(ring, k + 1)[lane * PEEL_STRIDE], 0ull);
-        if (k == 1)
-            for (int q = 0; q < nown; ++q) peel_transpose(mask, rowm, wit, Mp, W, uniform(sh.own[q]), sh);
+        int active = 0;
         for (int q = 0; q < nown; ++q) {
-            const int c = uniform(sh.own[q]);
-#ifdef NSGA3_PEEL_TRACE
-            if (threadIdx.x == 0 && k < 16) trace[2 * (k * W + c)] = __builtin_amdgcn_s_memrealtime();
-#endif
-            peel_chunk(nd, rowm, wit, W, ns, k, c, alive, rank, ring, sh);
-#ifdef NSGA3_PEEL_TRACE
-            if (threadIdx.x == 0 && k < 16) trace[2 * (k * W + c) + 1] = __builtin_amdgcn_s_memrealtime();
-#endif
+            const int b = uniform(sh.own_b[q]);
+            const int c = uniform(sh.own_c[q]);
+            const int cum_prev = uniform(sh.own_cum[q]);
+            if (cum_prev < 0) continue;  // this instance finished
+            const Inst &I = bv.tab[b];
+            // wait for front k - 1 of the instance
+            if (wv == 0) {
+                const u64 *slot = peel_slot(I.P.facc, k - 1);
+                u64 v = 0;
+                int ok = 1;
+                for (unsigned polls = 0;; ++polls) {
+                    // lanes 0..31 read one shard each; the wave sums (count, size)
+                    const u64 part = lane < PEEL_SHARDS ? load_relaxed(&slot[lane * PEEL_STRIDE]) : 0ull;
+                    v = uniform(wave_sum(part));
+                    if ((unsigned)(v & 0xffffffffull) >= (unsigned)I.W) break;
+                    if (polls == (1u << 26)) { ok = 0; break; }
+                    __builtin_amdgcn_s_sleep(2);
+                }
+                sh.val = v;
+                sh.flag = ok;
+            }
+            __syncthreads();
+            const u64 v = uniform(sh.val);
+            const int ok = uniform(sh.flag);
+            // alive slots are reused only after ns fronts: then cached copies of the
+            // slot read ns fronts ago must be dropped before it is read again
+            if (k + 1 >= I.ns) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            __syncthreads();
+            const int size = (int)(v >> 32);
+            const int cum = cum_prev + size;
+            if (!ok || cum >= I.n_stop || size == 0) {
+                if (wv == 0) {
+                    if (!ok || size == 0) atomicOr(&I.P.ctrl->status, ST_INTERNAL);
+                    I.front_info[0] = k - 1;
+                    I.front_info[1] = cum_prev;
+                    I.front_info[2] = I.n_stop - cum_prev;
+                    I.front_info[3] = k;
+                    sh.own_cum[q] = -1;
+                }
+                continue;
+            }
+            if (wv == 0) {
+                sh.own_cum[q] = cum;
+                // clear the counters of front k + 1 (last read while waiting for
+                // front k - 2); this chunk's own front-k publish, which front k + 1
+                // waits for, is ordered after these stores
+                if (lane <= PEEL_SHARDS) store_relaxed(&peel_slot(I.P.facc, k + 1)[lane * PEEL_STRIDE], 0ull);
+            }
+            if (k == 1) peel_transpose(I, c, sh);
+            peel_chunk(I, k, c, sh);
+            active = 1;
         }
+        __syncthreads();
+        if (!active) break;
     }
 }
 
-hipError_t launch_nd_sort(const Layout &L, const Ptrs &P, const float *F, int n_stop, int *rank,
-                          int *front_info, bool reset_status, hipStream_t s) {
-    const int M = L.M, m = L.m, Mp = L.Mp, W = L.W;
-    NSGA3_LAUNCH("nd_init", k_nd_init, dim3(1), dim3(256), 0, s, P.ctrl, P.facc, front_info,
-                 n_stop, reset_status);
-    NSGA3_LAUNCH("nd_prep", k_nd_prep, dim3((Mp + 255) / 256), dim3(256), 0, s, F, M, m, Mp, P.ft,
-                       P.nd, rank, P.alive, P.ctrl);
-    const int G = 8;
-    long long n_items = (long long)W + (long long)G * ((W / G) * (long long)(W / G - 1) / 2) +
-                        (long long)(W / G) * (W % G);
-    const unsigned blocks = (unsigned)((n_items + 3) / 4);
-#define NSGA3_DOM_CASE(MO)                                                                   \
-    case MO:                                                                                 \
-        NSGA3_LAUNCH("dominance", k_dominance<MO>, dim3(blocks), dim3(256), 0, s, P.ft, Mp, W, G,  \
-                           n_items, P.mask, P.nd);                                           \
+hipError_t launch_prepare(const HostPlan &hp, const BatchView &bv, hipStream_t s) {
+    NSGA3_LAUNCH("init", k_init, dim3(hp.B), dim3(256), 0, s, bv);
+    NSGA3_LAUNCH("prep", k_prep, dim3((hp.npt + hp.nref) / 256), dim3(256), 0, s, bv, hp.npt);
+    return hipGetLastError();
+}
+
+hipError_t launch_nd_sort(const HostPlan &hp, const BatchView &bv, hipStream_t s) {
+    for (int g = 0; g < hp.ngroups; ++g) {
+        const int gs = hp.grp_start[g], gn = hp.grp_start[g + 1] - gs;
+        const long long item0 = hp.grp_dom[g], n_items = hp.grp_dom[g + 1] - item0;
+        const unsigned blocks = (unsigned)((n_items + 3) / 4);
+#define NSGA3_DOM_CASE(MO)                                                                       \
+    case MO:                                                                                     \
+        NSGA3_LAUNCH("dominance", k_dominance<MO>, dim3(blocks), dim3(256), 0, s, bv, gs, gn,   \
+                     item0, n_items);                                                            \
         break;
-    switch (m) {
-        NSGA3_DOM_CASE(2) NSGA3_DOM_CASE(3) NSGA3_DOM_CASE(4) NSGA3_DOM_CASE(5)
-        NSGA3_DOM_CASE(6) NSGA3_DOM_CASE(7) NSGA3_DOM_CASE(8) NSGA3_DOM_CASE(9)
-        NSGA3_DOM_CASE(10) NSGA3_DOM_CASE(11) NSGA3_DOM_CASE(12) NSGA3_DOM_CASE(13)
-        NSGA3_DOM_CASE(14) NSGA3_DOM_CASE(15) NSGA3_DOM_CASE(16)
-        default: return hipErrorInvalidValue;
-    }
+        switch (hp.grp_m[g]) {
+            NSGA3_DOM_CASE(2) NSGA3_DOM_CASE(3) NSGA3_DOM_CASE(4) NSGA3_DOM_CASE(5)
+            NSGA3_DOM_CASE(6) NSGA3_DOM_CASE(7) NSGA3_DOM_CASE(8) NSGA3_DOM_CASE(9)
+            NSGA3_DOM_CASE(10) NSGA3_DOM_CASE(11) NSGA3_DOM_CASE(12) NSGA3_DOM_CASE(13)
+            NSGA3_DOM_CASE(14) NSGA3_DOM_CASE(15) NSGA3_DOM_CASE(16)
+            default: return hipErrorInvalidValue;
+        }
 #undef NSGA3_DOM_CASE
-    const int peel_blocks = W < 3 * device_info().cus ? W : 3 * device_info().cus;
-    NSGA3_LAUNCH("peel", k_peel, dim3(peel_blocks), dim3(64 * PEEL_WAVES), 0, s, P.mask, P.nd, M,
-                 Mp, W, n_stop, L.ns, P.alive, rank, P.facc, P.rowm, P.wit, P.ctrl, front_info
-#ifdef NSGA3_PEEL_TRACE
-                 , P.akey
-#endif
-                 );
+    }
+    const int cap = 3 * device_info().cus;
+    const int peel_blocks = hp.nchunk < cap ? hp.nchunk : cap;
+    NSGA3_LAUNCH("peel", k_peel, dim3(peel_blocks), dim3(64 * PEEL_WAVES), 0, s, bv, hp.nchunk);
     return hipGetLastError();
 }
 

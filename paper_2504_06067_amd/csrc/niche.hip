@@ -14,10 +14,12 @@
 // level 0, otherwise candidate (key(seed, 2, j, L) mod remaining) in
 // ascending index order. The result equals the one-pick-per-iteration loop.
 //
+// For a batch of independent instances (counters are zeroed by k_prep).
+//
 // Kernels:
-//   k_niche_init     zero counters and flags
-//   k_niche_count    rho (fronts < l) and c (front l) per reference
-//   k_niche_plan     one workgroup: CSR offsets, L*, radix select of the r
+//   k_niche_count    rho (fronts < l) and c (front l) per reference (stage
+//                    call; a whole selection counts in the association)
+//   k_niche_plan     one workgroup per instance: CSR offsets, L*, radix select of the r
 //                    least keys, per-reference pick counts t_j
 //   k_niche_scatter  members of front l into per-reference segments
 //   k_niche_pick     one wave per reference: sort its segment ascending,
@@ -29,35 +31,23 @@ namespace nsga3 {
 
 constexpr int PLAN_THREADS = 1024;
 constexpr int PICK_CAP = 2048;          // segment length kept in LDS by one wave
-constexpr int TILE = 4096;              // compaction tile
+constexpr int TILE = COMPACT_TILE;      // compaction tile
 
-__global__ __launch_bounds__(256) void k_niche_init(int H, int M, int *rho, int *cnt, int *fill,
-                                                     int *picked, Ctrl *ctrl, bool reset_status) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t == 0 && reset_status) ctrl->status = 0;
-    if (t < H) {
-        rho[t] = 0;
-        cnt[t] = 0;
-        fill[t] = 0;
-    }
-    if (t < M) picked[t] = 0;
-}
-
-__global__ __launch_bounds__(256) void k_niche_count(const int *__restrict__ rank,
-                                                      const int *__restrict__ front_info,
-                                                      const int *__restrict__ pi, int M, int H,
-                                                      int *rho, int *cnt, Ctrl *ctrl) {
-    const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    if (x >= M) return;
-    const int l = front_info[0];
-    const int r = rank[x];
+// Stage call only (a whole selection counts in the association's final pass).
+__global__ __launch_bounds__(256) void k_niche_count(BatchView bv) {
+    const Local L = locate(bv.pt_pref, bv.B);
+    const Inst &I = bv.tab[L.b];
+    const int x = L.i;
+    if (x >= I.M) return;
+    const int l = I.front_info[0];
+    const int r = I.rank[x];
     if (r < 0 || r > l) return;
-    const int p = pi[x];
-    if (p < 0 || p >= H) {
-        atomicOr(&ctrl->status, ST_INTERNAL);
+    const int p = I.pi[x];
+    if (p < 0 || p >= I.H) {
+        atomicOr(&I.P.ctrl->status, ST_INTERNAL);
         return;
     }
-    atomicAdd(r < l ? &rho[p] : &cnt[p], 1);
+    atomicAdd(r < l ? &I.P.rho[p] : &I.P.cnt[p], 1);
 }
 
 __device__ __forceinline__ long long block_sum_ll(long long v, long long *red) {
@@ -86,11 +76,16 @@ __device__ __forceinline__ long long block_max_ll(long long v, long long *red) {
     return uniform(m);
 }
 
-__global__ __launch_bounds__(PLAN_THREADS) void k_niche_plan(const int *__restrict__ front_info,
-                                                              const int *__restrict__ rho,
-                                                              const int *__restrict__ cnt, int H,
-                                                              u64 seed, int *off, int *tpick,
-                                                              Ctrl *ctrl) {
+// One workgroup per instance.
+__global__ __launch_bounds__(PLAN_THREADS) void k_niche_plan(BatchView bv) {
+    const Inst &I = bv.tab[blockIdx.x];
+    const int *__restrict__ rho = I.P.rho;
+    const int *__restrict__ cnt = I.P.cnt;
+    const int H = I.H;
+    const u64 seed = I.seed;
+    int *off = I.P.off;
+    int *tpick = I.P.tpick;
+    Ctrl *ctrl = I.P.ctrl;
     __shared__ long long red[PLAN_THREADS / 64];
     __shared__ int part[PLAN_THREADS];
     __shared__ unsigned hist[256];
@@ -98,7 +93,7 @@ __global__ __launch_bounds__(PLAN_THREADS) void k_niche_plan(const int *__restri
     const int tid = threadIdx.x;
     const int wv = uniform((int)(threadIdx.x >> 6));
     const int lane = lane_id();
-    const int K = uniform(front_info[2]);
+    const int K = uniform(I.front_info[2]);
 
     // thread tid owns the contiguous references [b0, b1)
     const int per = (H + PLAN_THREADS - 1) / PLAN_THREADS;
@@ -270,18 +265,16 @@ __global__ __launch_bounds__(PLAN_THREADS) void k_niche_plan(const int *__restri
     }
 }
 
-__global__ __launch_bounds__(256) void k_niche_scatter(const int *__restrict__ rank,
-                                                        const int *__restrict__ front_info,
-                                                        const int *__restrict__ pi, int M, int H,
-                                                        const int *__restrict__ off, int *fill,
-                                                        int *members) {
-    const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    if (x >= M) return;
-    if (rank[x] != front_info[0]) return;
-    const int p = pi[x];
-    if (p < 0 || p >= H) return;
-    const int slot = atomicAdd(&fill[p], 1);
-    members[off[p] + slot] = x;
+__global__ __launch_bounds__(256) void k_niche_scatter(BatchView bv) {
+    const Local L = locate(bv.pt_pref, bv.B);
+    const Inst &I = bv.tab[L.b];
+    const int x = L.i;
+    if (x >= I.M) return;
+    if (I.rank[x] != I.front_info[0]) return;
+    const int p = I.pi[x];
+    if (p < 0 || p >= I.H) return;
+    const int slot = atomicAdd(&I.P.fill[p], 1);
+    I.P.members[I.P.off[p] + slot] = x;
 }
 
 // Makes every lane's earlier LDS and global writes visible to the other lanes
@@ -341,19 +334,26 @@ __device__ __forceinline__ int select_bit(u64 w, int k) {
 
 // One wave per reference (4 per workgroup). Segments up to PICK_CAP are
 // sorted and tracked in LDS; longer ones in place in global memory.
-__global__ __launch_bounds__(256) void k_niche_pick(const int *__restrict__ rho,
-                                                     const int *__restrict__ cnt,
-                                                     const int *__restrict__ off,
-                                                     const int *__restrict__ tpick,
-                                                     const float *__restrict__ dist, int H,
-                                                     u64 seed, int *members, u64 *remain_g,
-                                                     int *picked) {
+// Grid: all instances' padded reference ranges, four references per block.
+__global__ __launch_bounds__(256) void k_niche_pick(BatchView bv) {
     __shared__ int s_buf[4][PICK_CAP];
     __shared__ u64 s_rem[4][PICK_CAP / 64];
+    const int base = uniform((int)(blockIdx.x * 4));
+    const int b = uniform(find_range(bv.ref_pref, bv.B, base));
+    const Inst &I = bv.tab[b];
+    const int *__restrict__ rho = I.P.rho;
+    const int *__restrict__ cnt = I.P.cnt;
+    const int *__restrict__ off = I.P.off;
+    const int *__restrict__ tpick = I.P.tpick;
+    const float *__restrict__ dist = I.dist;
+    const u64 seed = I.seed;
+    int *members = I.P.members;
+    u64 *remain_g = I.P.remain;
+    int *picked = I.P.picked;
     const int wv = threadIdx.x >> 6;
     const int lane = lane_id();
-    const int j = blockIdx.x * 4 + wv;
-    if (j >= H) return;
+    const int j = base - bv.ref_pref[b] + wv;
+    if (j >= I.H) return;
     const int t = tpick[j];
     if (t <= 0) return;
     const int c = cnt[j];
@@ -437,47 +437,49 @@ __global__ __launch_bounds__(256) void k_niche_pick(const int *__restrict__ rho,
     }
 }
 
-// Compaction of {x : rank[x] < l or picked[x]} in ascending order.
-__global__ __launch_bounds__(256) void k_compact_count(const int *__restrict__ rank,
-                                                        const int *__restrict__ front_info,
-                                                        const int *__restrict__ picked, int M,
-                                                        int *tiles) {
+// Compaction of {x : rank[x] < l or picked[x]} in ascending order; grid: all
+// instances' tiles.
+__global__ __launch_bounds__(256) void k_compact_count(BatchView bv) {
     __shared__ long long red[4];
-    const int l = front_info[0];
-    const int base = blockIdx.x * TILE;
+    const int b = uniform(find_range(bv.tile_pref, bv.B, (int)blockIdx.x));
+    const Inst &I = bv.tab[b];
+    const int l = I.front_info[0];
+    const int M = I.M;
+    const int tile = (int)blockIdx.x - bv.tile_pref[b];
+    const int base = tile * TILE;
     long long c = 0;
     for (int i = threadIdx.x; i < TILE; i += 256) {
         const int x = base + i;
         if (x < M) {
-            const int r = rank[x];
-            c += (r >= 0 && r < l) || picked[x];
+            const int r = I.rank[x];
+            c += (r >= 0 && r < l) || I.P.picked[x];
         }
     }
     c = block_sum_ll(c, red);
-    if (threadIdx.x == 0) tiles[blockIdx.x] = (int)c;
+    if (threadIdx.x == 0) I.P.tiles[tile] = (int)c;
 }
 
-__global__ __launch_bounds__(256) void k_compact_write(const int *__restrict__ rank,
-                                                        const int *__restrict__ front_info,
-                                                        const int *__restrict__ picked,
-                                                        const int *__restrict__ tiles, int ntiles,
-                                                        int M, int N, int *selected, Ctrl *ctrl) {
+__global__ __launch_bounds__(256) void k_compact_write(BatchView bv) {
     __shared__ long long red[4];
     __shared__ int wsum[4];
-    const int l = front_info[0];
+    const int b = uniform(find_range(bv.tile_pref, bv.B, (int)blockIdx.x));
+    const Inst &I = bv.tab[b];
+    const int l = I.front_info[0];
+    const int M = I.M, N = I.N;
+    const int tile = (int)blockIdx.x - bv.tile_pref[b];
     long long before = 0;
-    for (int b = threadIdx.x; b < (int)blockIdx.x; b += 256) before += tiles[b];
+    for (int t = threadIdx.x; t < tile; t += 256) before += I.P.tiles[t];
     before = block_sum_ll(before, red);
     // thread t owns TILE/256 = 16 consecutive points
     constexpr int PER = TILE / 256;
-    const int x0 = blockIdx.x * TILE + threadIdx.x * PER;
+    const int x0 = tile * TILE + threadIdx.x * PER;
     int flags = 0, n = 0;
     for (int q = 0; q < PER; ++q) {
         const int x = x0 + q;
         int f = 0;
         if (x < M) {
-            const int r = rank[x];
-            f = (r >= 0 && r < l) || picked[x];
+            const int r = I.rank[x];
+            f = (r >= 0 && r < l) || I.P.picked[x];
         }
         flags |= f << q;
         n += f;
@@ -491,35 +493,24 @@ __global__ __launch_bounds__(256) void k_compact_write(const int *__restrict__ r
     int pos = (int)before + woff + incl - n;
     for (int q = 0; q < PER; ++q) {
         if ((flags >> q) & 1) {
-            if (pos < N) selected[pos] = x0 + q;
+            if (pos < N) I.selected[pos] = x0 + q;
             ++pos;
         }
     }
-    if (blockIdx.x == (unsigned)(ntiles - 1) && threadIdx.x == 255) {
-        if (pos != N) atomicOr(&ctrl->status, ST_INTERNAL);
+    if (tile == I.ntiles - 1 && threadIdx.x == 255) {
+        if (pos != N) atomicOr(&I.P.ctrl->status, ST_INTERNAL);
     }
 }
 
-hipError_t launch_niche(const Layout &L, const Ptrs &P, const int *rank, const int *front_info,
-                        const int *pi, const float *dist, u64 seed, int *selected,
-                        bool reset_status, hipStream_t s) {
-    const int M = L.M, H = L.H, N = L.N;
-    const int nt = M > H ? M : H;
-    NSGA3_LAUNCH("niche_init", k_niche_init, dim3((nt + 255) / 256), dim3(256), 0, s, H, M, P.rho, P.cnt,
-                       P.fill, P.picked, P.ctrl, reset_status);
-    NSGA3_LAUNCH("niche_count", k_niche_count, dim3((M + 255) / 256), dim3(256), 0, s, rank, front_info,
-                       pi, M, H, P.rho, P.cnt, P.ctrl);
-    NSGA3_LAUNCH("niche_plan", k_niche_plan, dim3(1), dim3(PLAN_THREADS), 0, s, front_info, P.rho, P.cnt,
-                       H, seed, P.off, P.tpick, P.ctrl);
-    NSGA3_LAUNCH("niche_scatter", k_niche_scatter, dim3((M + 255) / 256), dim3(256), 0, s, rank, front_info,
-                       pi, M, H, P.off, P.fill, P.members);
-    NSGA3_LAUNCH("niche_pick", k_niche_pick, dim3((H + 3) / 4), dim3(256), 0, s, P.rho, P.cnt, P.off,
-                       P.tpick, dist, H, seed, P.members, P.remain, P.picked);
-    const int ntiles = (M + TILE - 1) / TILE;
-    NSGA3_LAUNCH("compact_count", k_compact_count, dim3(ntiles), dim3(256), 0, s, rank, front_info, P.picked,
-                       M, P.tiles);
-    NSGA3_LAUNCH("compact_write", k_compact_write, dim3(ntiles), dim3(256), 0, s, rank, front_info, P.picked,
-                       P.tiles, ntiles, M, N, selected, P.ctrl);
+hipError_t launch_niche(const HostPlan &hp, const BatchView &bv, hipStream_t s) {
+    const unsigned pblocks = (unsigned)(hp.npt / 256);
+    if (!(bv.run & RUN_ASSOC))
+        NSGA3_LAUNCH("niche_count", k_niche_count, dim3(pblocks), dim3(256), 0, s, bv);
+    NSGA3_LAUNCH("niche_plan", k_niche_plan, dim3(hp.B), dim3(PLAN_THREADS), 0, s, bv);
+    NSGA3_LAUNCH("niche_scatter", k_niche_scatter, dim3(pblocks), dim3(256), 0, s, bv);
+    NSGA3_LAUNCH("niche_pick", k_niche_pick, dim3((unsigned)(hp.nref / 4)), dim3(256), 0, s, bv);
+    NSGA3_LAUNCH("compact_count", k_compact_count, dim3(hp.ntile), dim3(256), 0, s, bv);
+    NSGA3_LAUNCH("compact_write", k_compact_write, dim3(hp.ntile), dim3(256), 0, s, bv);
     return hipGetLastError();
 }
 

@@ -1,5 +1,14 @@
-// Internal declarations of libnsga3: workspace layout, the device control
-// block, device helpers shared by the kernels, and the host-side launchers.
+// Internal declarations of libnsga3: the per-instance descriptor and batch
+// view that every kernel reads, the device control block, device helpers
+// shared by the kernels, and the host-side launchers.
+//
+// Every kernel works on a batch of independent selection instances (a plain
+// call is a batch of one). Each instance has its own workspace region and a
+// descriptor with absolute device pointers; the descriptors and the prefix
+// arrays that map a global work index to (instance, local index) live in the
+// batch header region of the workspace, written there by a copy kernel whose
+// arguments carry the bytes (so a whole call is kernel launches only, and can
+// be captured in a HIP graph).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -20,32 +29,45 @@ enum : int {
     ST_INTERNAL = 4,
 };
 
-// Device-resident control block at offset 0 of every workspace.
+// Which stages a call runs (selects the resets and the optional fusions).
+enum : int {
+    RUN_ND = 1,
+    RUN_NORM = 2,
+    RUN_ASSOC = 4,
+    RUN_NICHE = 8,
+    RUN_SELECT = 15,
+};
+
+// Device-resident control block at the start of every instance's workspace.
 struct Ctrl {
     int status;
-    int front_info[4];      // {l, |S|, K, fronts}: written by the peel
-    u64 ticket;             // peel work-queue tickets
-    u64 completed;          // peel items completed
-    int ranked;             // points ranked so far
-    unsigned finished;      // peel finished flag
-    int list_count;         // length of the S_t index list
+    int list_count;          // length of the S_t index list
     unsigned zmin_enc[NSGA3_MAX_OBJECTIVES];   // ideal point, order-preserving encoding
     unsigned fmax_enc[NSGA3_MAX_OBJECTIVES];   // largest objective over S_t, same encoding
     u64 ext_key[NSGA3_MAX_OBJECTIVES];         // (ASF bits << 32) | index, min-reduced
     float zf[NSGA3_MAX_OBJECTIVES];            // ideal point
     float recip[NSGA3_MAX_OBJECTIVES];         // 1 / intercept, float32
-    int lstar;              // water-fill level L*
-    int rpick;              // picks made at level L*
-    int all_pick;           // 1 if the whole last front is taken
-    int fl_total;           // |F_l|
-    // normalization outputs of nsga3_select (the stage call writes the caller's)
+    int lstar;               // water-fill level L*
+    int rpick;               // picks made at level L*
+    int all_pick;            // 1 if the whole last front is taken
+    int fl_total;            // |F_l|
+    int front_info[4];       // front_info of nsga3_select (stage calls use the caller's)
     float ideal_out[NSGA3_MAX_OBJECTIVES];
     double icpt_out[NSGA3_MAX_OBJECTIVES];
     int ext_out[NSGA3_MAX_OBJECTIVES];
     int degen_out;
 };
 
-// Byte offsets of every workspace region (all 256-byte aligned).
+// front-peeling ring of completion counters: 3 slots of 32 shard counters,
+// each on its own 256-byte line
+constexpr int PEEL_SHARDS = 32;
+constexpr int PEEL_STRIDE = 32;  // u64 words between counters
+constexpr int PEEL_SLOT = (PEEL_SHARDS + 1) * PEEL_STRIDE;
+constexpr int ALIVE_PAD = 16;    // u64 words per alive word (one 128-byte line)
+constexpr int PT_ALIGN = 256;    // per-instance point and reference ranges are padded to this
+constexpr int COMPACT_TILE = 4096;  // points per output-compaction tile
+
+// Byte offsets of one instance's workspace regions (all 256-byte aligned).
 struct Layout {
     int M, m, H, N, Mp, W, Hp, ns;
     size_t ctrl, ft, nd, mask, rowm, wit, alive, facc, list, fn, rank, pi, dist, akey, wn,
@@ -62,8 +84,8 @@ struct Ptrs {
     u64 *rowm;
     int *wit;
     u64 *alive;
-    int *list;
     u64 *facc;
+    int *list;
     float *fn;
     int *rank, *pi;
     float *dist;
@@ -76,7 +98,60 @@ struct Ptrs {
 
 Ptrs carve(const Layout &L, void *ws);
 
+// One instance as the kernels see it.
+struct Inst {
+    const float *F;
+    const float *Z;
+    int *rank;          // in/out ranks
+    int *front_info;    // in/out {l, |S|, K, l + 1}
+    float *Fn;          // normalized objectives
+    int *pi;
+    float *dist;
+    int *selected;
+    float *ideal;
+    double *intercept;
+    int *extreme;
+    int *degenerate;
+    Ptrs P;
+    u64 seed;
+    int M, m, H, N, Mp, W, Hp, ns;
+    int n_stop;
+    int G;              // dominance: column tiles per work item
+    int R, nslice;      // association: references per slice, slices
+    int ntiles;         // compaction tiles
+};
+
+// Global index ranges: instance b owns [pref[b], pref[b+1]) of each kind.
+// Point and reference ranges are padded to PT_ALIGN so that no 256-thread
+// block straddles two instances. dom_pref / asc_pref run over `order`
+// (instances sorted by m) and count per-wave work items.
+struct BatchView {
+    const Inst *tab;
+    const int *pt_pref;
+    const int *ref_pref;
+    const int *chunk_pref;
+    const int *tile_pref;
+    const int *order;
+    const long long *dom_pref;
+    const long long *asc_pref;
+    u64 *ticket;        // batch-level peel ticket counter
+    int B;
+    int run;            // RUN_* flags of this call
+};
+
 // ------------------------------------------------------------ device helpers
+
+// Largest b in [0, n) with pref[b] <= x (pref[0] <= x < pref[n]).
+template <typename T>
+__device__ __forceinline__ int find_range(const T *pref, int n, T x) {
+    int lo = 0, hi = n;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (pref[mid] <= x) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
 
 __device__ __forceinline__ u64 sm64(u64 x) {
     u64 z = x + 0x9E3779B97F4A7C15ull;
@@ -168,14 +243,29 @@ __device__ __forceinline__ int wave_incl_scan(int v) {
     return v;
 }
 
-__device__ __forceinline__ unsigned load_acquire(const unsigned *p) {
-    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+__device__ __forceinline__ u64 load_relaxed(const u64 *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ __forceinline__ int load_acquire(const int *p) {
-    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+__device__ __forceinline__ int load_relaxed(const int *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ __forceinline__ u64 load_acquire(const u64 *p) {
-    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+__device__ __forceinline__ void store_relaxed(u64 *p, u64 v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void store_relaxed(int *p, int v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// (instance, local index) of a thread of a point- or reference-parallel
+// kernel with 256-thread blocks over ranges padded to PT_ALIGN.
+struct Local {
+    int b;      // instance
+    int i;      // local index of this thread
+};
+__device__ __forceinline__ Local locate(const int *pref, int B) {
+    const int base = uniform((int)(blockIdx.x * blockDim.x));
+    const int b = uniform(find_range(pref, B, base));
+    return Local{b, base - pref[b] + (int)threadIdx.x};
 }
 
 // ---------------------------------------------------------- instrumentation
@@ -205,20 +295,27 @@ struct Dev {
 };
 Dev device_info();
 
-// non-dominated sort
-hipError_t launch_nd_sort(const Layout &L, const Ptrs &P, const float *F, int n_stop,
-                          int *rank, int *front_info, bool reset_status, hipStream_t s);
-// normalization
-hipError_t launch_normalize(const Layout &L, const Ptrs &P, const float *F, const int *rank,
-                            const int *front_info, float *Fn, float *ideal, double *intercept,
-                            int *extreme, int *degenerate, bool reset_status, hipStream_t s);
-// association
-hipError_t launch_associate(const Layout &L, const Ptrs &P, const float *Fn, const int *rank,
-                            const int *front_info, const float *Z, int *pi, float *dist,
-                            bool reset_status, hipStream_t s);
-// niching
-hipError_t launch_niche(const Layout &L, const Ptrs &P, const int *rank, const int *front_info,
-                        const int *pi, const float *dist, u64 seed, int *selected,
-                        bool reset_status, hipStream_t s);
+// Host-side plan of one call: totals and the m-groups of the batch.
+struct HostPlan {
+    int B;
+    int npt, nref, nchunk, ntile;
+    int ngroups;
+    int grp_m[NSGA3_MAX_OBJECTIVES + 1];
+    int grp_start[NSGA3_MAX_OBJECTIVES + 2];       // range of `order` per group
+    long long grp_dom[NSGA3_MAX_OBJECTIVES + 2];   // dominance items before each group
+    long long grp_asc[NSGA3_MAX_OBJECTIVES + 2];   // association items before each group
+    int max_W;
+};
+
+hipError_t launch_prepare(const HostPlan &hp, const BatchView &bv, hipStream_t s);
+hipError_t launch_nd_sort(const HostPlan &hp, const BatchView &bv, hipStream_t s);
+hipError_t launch_normalize(const HostPlan &hp, const BatchView &bv, hipStream_t s);
+hipError_t launch_associate(const HostPlan &hp, const BatchView &bv, hipStream_t s);
+hipError_t launch_niche(const HostPlan &hp, const BatchView &bv, hipStream_t s);
+
+// dominance work items of an instance (waves): block row jb holds
+// floor(jb / G) + 1 items of up to G column tiles each
+constexpr int DOM_G_DEFAULT = 8;
+long long dominance_items(int W, int G);
 
 }  // namespace nsga3

@@ -44,11 +44,16 @@ def lib():
     L.nsga3_niche.argtypes = [P, P, P, P, i32, i32, i32, u64, P, P, sz, P]
     L.nsga3_select.argtypes = [P, i32, i32, P, i32, i32, u64, P, P, P, P, P, sz, P]
     L.nsga3_read_status.argtypes = [P, P, P]
+    L.nsga3_batched_workspace_bytes.argtypes = [P, i32]
+    L.nsga3_batched_workspace_bytes.restype = sz
+    L.nsga3_select_batched.argtypes = [P, i32, P, sz, P]
+    L.nsga3_read_status_batched.argtypes = [P, i32, P, P, P]
     L.nsga3_version.restype = ctypes.c_char_p
     L.nsga3_profile_enable.argtypes = [ctypes.c_char_p]
     L.nsga3_profile_read.argtypes = [ctypes.c_char_p, P, P, P]
     for f in ("nsga3_nd_sort", "nsga3_normalize", "nsga3_associate", "nsga3_niche",
-              "nsga3_select", "nsga3_read_status", "nsga3_profile_enable", "nsga3_profile_read"):
+              "nsga3_select", "nsga3_read_status", "nsga3_profile_enable", "nsga3_profile_read",
+              "nsga3_select_batched", "nsga3_read_status_batched"):
         getattr(L, f).restype = i32
     _lib = L
     return L
@@ -192,6 +197,92 @@ def select(F, Z, N, seed, ws=None, out=None, intermediates=False):
     if intermediates:
         return dict(selected=sel, rank=rank, pi=pi, dist=dist)
     return sel
+
+
+class Instance(ctypes.Structure):
+    """``nsga3_instance`` of the C header."""
+    _fields_ = [("F", ctypes.c_void_p), ("Z", ctypes.c_void_p), ("selected", ctypes.c_void_p),
+                ("rank", ctypes.c_void_p), ("pi", ctypes.c_void_p), ("dist", ctypes.c_void_p),
+                ("M", ctypes.c_int32), ("m", ctypes.c_int32), ("H", ctypes.c_int32),
+                ("N", ctypes.c_int32), ("seed", ctypes.c_uint64), ("tile", ctypes.c_int32 * 4)]
+
+
+class Batch:
+    """A batch of independent selections run by one nsga3_select_batched call.
+
+    problems: sequence of dicts with F [M][m] and Z [H][m] (float32 CUDA), N,
+    seed and optionally tile (up to 4 ints, 0 = automatic). Outputs are
+    allocated once here: ``selected[b]`` and, with intermediates=True,
+    ``rank[b]``, ``pi[b]``, ``dist[b]``. ``run()`` enqueues the call on the
+    current stream; it may be repeated (and captured in a graph)."""
+
+    def __init__(self, problems, ws=None, intermediates=False):
+        if not problems:
+            raise ValueError("empty batch")
+        self.B = len(problems)
+        self.arr = (Instance * self.B)()
+        self.selected, self.rank, self.pi, self.dist = [], [], [], []
+        self._keep = []
+        dev = None
+        for b, q in enumerate(problems):
+            F, Z = _f32(q["F"], "F", 2), _f32(q["Z"], "Z", 2)
+            if dev is None:
+                dev = F.device
+            if F.device != dev or Z.device != dev:
+                raise ValueError("all instances must be on one device")
+            M, m = F.shape
+            H = Z.shape[0]
+            if Z.shape[1] != m:
+                raise ValueError("Z must have m columns")
+            N = int(q["N"])
+            sel = torch.empty(N, dtype=torch.int32, device=dev)
+            self.selected.append(sel)
+            r = p_ = d = None
+            if intermediates:
+                r = torch.empty(M, dtype=torch.int32, device=dev)
+                p_ = torch.empty(M, dtype=torch.int32, device=dev)
+                d = torch.empty(M, dtype=torch.float32, device=dev)
+            self.rank.append(r)
+            self.pi.append(p_)
+            self.dist.append(d)
+            self._keep += [F, Z]
+            e = self.arr[b]
+            e.F, e.Z, e.selected = F.data_ptr(), Z.data_ptr(), sel.data_ptr()
+            e.rank = r.data_ptr() if r is not None else None
+            e.pi = p_.data_ptr() if p_ is not None else None
+            e.dist = d.data_ptr() if d is not None else None
+            e.M, e.m, e.H, e.N = M, m, H, N
+            e.seed = int(q["seed"]) & (2**64 - 1)
+            t = list(q.get("tile") or [])
+            for i in range(4):
+                e.tile[i] = int(t[i]) if i < len(t) else 0
+        self.device = dev
+        self.ws = ws or Workspace(dev)
+        nbytes = int(lib().nsga3_batched_workspace_bytes(self.arr, self.B))
+        if nbytes == 0:
+            raise Nsga3Error(EINVAL, "nsga3_batched_workspace_bytes")
+        self.buf = self.ws.get(nbytes)
+
+    def run(self):
+        _check(lib().nsga3_select_batched(self.arr, self.B, _ptr(self.buf), self.buf.numel(),
+                                          _stream(self.device)), "nsga3_select_batched")
+        return self.selected
+
+    def status(self):
+        """Per-instance status codes of the last run (waits for the stream)."""
+        st = (ctypes.c_int32 * self.B)()
+        _check(lib().nsga3_read_status_batched(self.arr, self.B, _ptr(self.buf),
+                                               _stream(self.device), st),
+               "nsga3_read_status_batched")
+        return list(st)
+
+
+def batched_workspace_bytes(problems):
+    """Workspace bytes of a batch given (M, m, H, N) tuples (0 if rejected)."""
+    arr = (Instance * len(problems))()
+    for e, (M, m, H, N) in zip(arr, problems):
+        e.M, e.m, e.H, e.N = M, m, H, N
+    return int(lib().nsga3_batched_workspace_bytes(arr, len(problems)))
 
 
 def version():

@@ -71,3 +71,63 @@ def test_invalid_arguments_enqueue_nothing(lib):
     # m out of range
     assert lib.nsga3_select(fake, 10, 17, fake, 5, 5, 0, fake, None, None, None, fake, 1 << 30,
                             None) == -1
+
+
+class _Inst(ctypes.Structure):
+    _fields_ = [("F", ctypes.c_void_p), ("Z", ctypes.c_void_p), ("selected", ctypes.c_void_p),
+                ("rank", ctypes.c_void_p), ("pi", ctypes.c_void_p), ("dist", ctypes.c_void_p),
+                ("M", ctypes.c_int32), ("m", ctypes.c_int32), ("H", ctypes.c_int32),
+                ("N", ctypes.c_int32), ("seed", ctypes.c_uint64), ("tile", ctypes.c_int32 * 4)]
+
+
+def _batch(shapes, tiles=None):
+    arr = (_Inst * len(shapes))()
+    for b, (M, m, H, N) in enumerate(shapes):
+        arr[b].M, arr[b].m, arr[b].H, arr[b].N = M, m, H, N
+        for i, t in enumerate((tiles or {}).get(b, [])):
+            arr[b].tile[i] = t
+    return arr
+
+
+def test_instance_struct_matches_header():
+    # six pointers, four int32, a uint64 and int32[4]
+    assert ctypes.sizeof(_Inst) == 88
+    src = open(os.path.join(ROOT, "include", "nsga3.h")).read()
+    body = src[src.index("typedef struct nsga3_instance"):src.index("} nsga3_instance;")]
+    fields = [ln.split(";")[0].split()[-1].lstrip("*") for ln in body.splitlines()[1:] if ";" in ln]
+    names = []
+    for f in fields:
+        names += [x.strip().lstrip("*") for x in f.split(",")]
+    assert names[:6] == ["F", "Z", "selected", "rank", "pi", "dist"]
+
+
+def test_batched_workspace_bytes(lib):
+    f = lib.nsga3_batched_workspace_bytes
+    f.restype = ctypes.c_size_t
+    f.argtypes = [ctypes.c_void_p, ctypes.c_int32]
+    one = _batch([(5000, 3, 91, 2500)])
+    # a batch of one holds what the plain call needs
+    assert f(one, 1) == lib.nsga3_workspace_bytes(5000, 3, 91, 2500)
+    two = _batch([(5000, 3, 91, 2500), (300, 10, 220, 150)])
+    assert f(two, 2) > f(one, 1) + lib.nsga3_workspace_bytes(300, 10, 220, 150) // 2
+    assert f(two, 0) == 0
+    assert f(None, 1) == 0
+    assert f(_batch([(5000, 3, 91, 2500)] * 2), 1025) == 0        # B above the limit
+    assert f(_batch([(1, 3, 91, 1)]), 1) == 0                     # bad shape
+    for t in ([65], [0, 7], [0, 0, 1], [0, 0, 0, 2], [-1], [0, 96]):
+        assert f(_batch([(5000, 3, 91, 2500)], {0: t}), 1) == 0, t
+    for t in ([1], [64, 16], [0, 91], [8, 80]):
+        assert f(_batch([(5000, 3, 91, 2500)], {0: t}), 1) > 0, t
+
+
+def test_batched_select_validates_before_enqueue(lib):
+    P = ctypes.c_void_p
+    lib.nsga3_select_batched.argtypes = [P, ctypes.c_int32, P, ctypes.c_size_t, P]
+    arr = _batch([(5000, 3, 91, 2500)])
+    # null pointers in the instance
+    assert lib.nsga3_select_batched(arr, 1, P(4096), 1 << 30, None) == -1
+    fake = 4096
+    arr[0].F = arr[0].Z = arr[0].selected = fake
+    assert lib.nsga3_select_batched(arr, 1, P(4096), 16, None) == -2      # ws too small
+    assert lib.nsga3_select_batched(arr, 1, P(4100), 1 << 30, None) == -1  # misaligned ws
+    assert lib.nsga3_select_batched(arr, 0, P(4096), 1 << 30, None) == -1  # empty batch

@@ -1,0 +1,183 @@
+"""Batched selection: every instance of a batch gets exactly what a plain
+nsga3_select on the same arguments gives (bit for bit, all intermediates),
+whatever the batch around it and whatever its tile parameters; the plain
+results are in turn checked against the oracle. Also: graph capture and
+replay of a batched call, and per-instance status words."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from gpu_util import device, to_dev, to_np
+from paper_2504_06067_amd import nsga3
+from paper_2504_06067_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+KEYS = ("selected", "rank", "pi", "dist")
+
+
+def mixed_instances(seed, count, lo=100, hi=6000):
+    """Uneven small instances over several m (and laws), oracle-sized."""
+    rng = np.random.default_rng(seed)
+    laws = ("exp", "cube", "sphere_half")
+    mp = {2: 60, 3: 12, 5: 5, 8: 3, 10: 3}
+    out = []
+    for b in range(count):
+        M = 2 * int(round(np.exp(rng.uniform(np.log(lo), np.log(hi))) / 2))
+        m = int(list(mp)[rng.integers(len(mp))])
+        F = wl.objectives(np.random.default_rng(seed * 100 + b), M, m, laws[b % 3])
+        Z = wl.das_dennis(m, mp[m])
+        N = int(rng.integers(1, M + 1)) if b % 4 == 3 else M // 2
+        out.append(dict(F=F, Z=Z, M=M, m=m, H=len(Z), N=N, seed=seed * 100 + b))
+    return out
+
+
+def as_problems(insts, dev, tiles=None):
+    probs = []
+    for b, q in enumerate(insts):
+        p = dict(F=to_dev(q["F"], dev), Z=to_dev(q["Z"], dev), N=q["N"], seed=q["seed"])
+        if tiles is not None:
+            p["tile"] = tiles[b]
+        probs.append(p)
+    return probs
+
+
+def run_batched(insts, dev, tiles=None):
+    bt = nsga3.Batch(as_problems(insts, dev, tiles), intermediates=True)
+    bt.run()
+    torch.cuda.synchronize()
+    assert bt.status() == [nsga3.OK] * len(insts)
+    return [{k: to_np(getattr(bt, k)[b]) for k in KEYS} for b in range(len(insts))]
+
+
+def run_plain(q, dev):
+    out = nsga3.select(to_dev(q["F"], dev), to_dev(q["Z"], dev), q["N"], q["seed"],
+                       intermediates=True)
+    return {k: to_np(v) for k, v in out.items()}
+
+
+def same(a, b):
+    return all(np.array_equal(a[k], b[k]) for k in KEYS)
+
+
+def check_oracle(q, g):
+    ref = oracle.select(q["F"], q["Z"], q["N"], q["seed"])
+    assert np.array_equal(g["rank"], ref["rank"])
+    _, fi = oracle.nd_sort(q["F"], q["N"])
+    chained = oracle.niche(g["rank"], fi, g["pi"], g["dist"].astype(np.float64), q["H"], q["N"],
+                           q["seed"])
+    assert np.array_equal(g["selected"], chained)
+    assert np.array_equal(g["selected"], ref["selected"]) or np.any(g["pi"] != ref["pi"])
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_batched_equals_plain_and_oracle(seed):
+    dev = device()
+    insts = mixed_instances(seed, 12)
+    got = run_batched(insts, dev)
+    for q, g in zip(insts, got):
+        assert same(g, run_plain(q, dev)), (q["M"], q["m"], q["N"])
+        check_oracle(q, g)
+
+
+def test_tile_invariance():
+    dev = device()
+    insts = mixed_instances(7, 8)
+    base = run_batched(insts, dev)
+    def slice_of(H, r):
+        if r == "H":
+            return H
+        return r if r <= H else H
+
+    for g_tile, r_tile in [(1, 16), (3, 0), (64, 32), (5, "H")]:
+        tiles = [[g_tile, slice_of(q["H"], r_tile), 0, 0] for q in insts]
+        got = run_batched(insts, dev, tiles)
+        for a, b in zip(base, got):
+            assert same(a, b), (g_tile, r_tile)
+
+
+def test_alone_equals_in_mix():
+    dev = device()
+    insts = mixed_instances(11, 10)
+    mix = run_batched(insts, dev)
+    for b in (0, 4, 9):
+        alone = run_batched([insts[b]], dev)[0]
+        assert same(alone, mix[b])
+    # and in another order
+    perm = [9, 3, 0, 7, 1, 8, 2, 6, 4, 5]
+    shuffled = run_batched([insts[i] for i in perm], dev)
+    for pos, i in enumerate(perm):
+        assert same(shuffled[pos], mix[i])
+
+
+def test_uneven_batch_full_size():
+    """The 64-instance uneven workload at full size: each instance equals its
+    plain run; the smallest few are also checked against the oracle."""
+    dev = device()
+    insts = wl.batched_instances(0, 64)
+    got = run_batched(insts, dev)
+    for q, g in zip(insts, got):
+        assert same(g, run_plain(q, dev)), (q["M"], q["m"])
+    for b in sorted(range(64), key=lambda i: insts[i]["M"])[:3]:
+        check_oracle(insts[b], got[b])
+
+
+def test_graph_replay():
+    dev = device()
+    insts = mixed_instances(5, 6)
+    bt = nsga3.Batch(as_problems(insts, dev), intermediates=True)
+    bt.run()
+    torch.cuda.synchronize()
+    eager = [{k: to_np(getattr(bt, k)[b]).copy() for k in KEYS} for b in range(len(insts))]
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        bt.run()  # warm-up on the side stream
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        bt.run()
+    for rep in range(4):
+        for b in range(len(insts)):
+            bt.selected[b].fill_(-7)
+            bt.rank[b].fill_(-7)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for b in range(len(insts)):
+            got = {k: to_np(getattr(bt, k)[b]) for k in KEYS}
+            assert same(got, eager[b]), (rep, b)
+        # eager work between replays
+        bt.run()
+        torch.cuda.synchronize()
+    assert bt.status() == [nsga3.OK] * len(insts)
+
+
+def test_status_per_instance():
+    dev = device()
+    insts = mixed_instances(3, 4)
+    bad = dict(insts[2])
+    F = bad["F"].copy()
+    F[5, 1] = np.nan
+    bad["F"] = F
+    insts[2] = bad
+    bt = nsga3.Batch(as_problems(insts, dev))
+    bt.run()
+    st = bt.status()
+    assert st[2] == nsga3.ENONFINITE
+    assert st[0] == st[1] == st[3] == nsga3.OK
+
+
+def test_batched_rejects_bad_arguments():
+    dev = device()
+    insts = mixed_instances(4, 2)
+    for tile in ([65, 0, 0, 0], [0, 7, 0, 0], [0, 0, 1, 0], [-1, 0, 0, 0]):
+        with pytest.raises(nsga3.Nsga3Error):
+            nsga3.Batch(as_problems(insts, dev, [tile, [0, 0, 0, 0]]))
+    bt = nsga3.Batch(as_problems(insts, dev))
+    small = bt.buf[: bt.buf.numel() // 2]
+    rc = nsga3.lib().nsga3_select_batched(bt.arr, bt.B, nsga3._ptr(small), small.numel(),
+                                          nsga3._stream(dev))
+    assert rc == nsga3.EWORKSPACE
