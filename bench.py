@@ -40,6 +40,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batched-reps", type=int, default=20)
+    ap.add_argument("--only-batched", action="store_true",
+                    help="run the batched comparison alone (for profiling it separately)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target CPU time of the oracle sample")
     return ap.parse_args()
@@ -167,6 +169,9 @@ def main():
     from paper_2504_06067_amd import nsga3, workloads
 
     dev = torch.device("cuda:0")
+    if args.only_batched:
+        print(json.dumps({"batched": bench_batched(args, dev)}), flush=True)
+        return
     inst = workloads.plain_instance(args.workload, args.seed)
     M, m, H, N = inst["M"], inst["m"], inst["H"], inst["N"]
     F = torch.from_numpy(inst["F"]).to(dev)

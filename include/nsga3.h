@@ -159,7 +159,8 @@ typedef struct nsga3_instance {
     int32_t M, m, H, N;   /* as nsga3_select */
     uint64_t seed;        /* tie-break seed, as nsga3_select */
     int32_t tile[4];      /* tile parameters, 0 = automatic: [0] column tiles of 64
-                           * points per dominance work item (1..64), [1] references
+                           * points per dominance work item (a power of two, 1..64),
+                           * [1] references
                            * per association slice (16..H, multiple of 16 unless H);
                            * [2], [3] must be 0. Results do not depend on them. */
 } nsga3_instance;

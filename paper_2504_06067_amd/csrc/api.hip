@@ -179,7 +179,7 @@ struct Plan {
 };
 
 static bool valid_tiles(const int *t, int H) {
-    if (t[0] < 0 || t[0] > 64) return false;
+    if (t[0] < 0 || t[0] > 64 || (t[0] & (t[0] - 1)) != 0) return false;
     if (t[1] < 0 || t[1] > H) return false;
     if (t[1] != 0 && t[1] != H && (t[1] < 16 || t[1] % 16 != 0)) return false;
     return t[2] == 0 && t[3] == 0;
@@ -270,14 +270,14 @@ static void plan(std::vector<Spec> &spec, char *ws, int run, Plan &p) {
 
     char *hd = ws + p.inst_total;
     BatchView &bv = p.bv;
-    bv.tab = (const Inst *)(hd + hl.tab);
-    bv.pt_pref = (const int *)(hd + hl.pt_pref);
-    bv.ref_pref = (const int *)(hd + hl.ref_pref);
-    bv.chunk_pref = (const int *)(hd + hl.chunk_pref);
-    bv.tile_pref = (const int *)(hd + hl.tile_pref);
-    bv.order = (const int *)(hd + hl.order);
-    bv.dom_pref = (const long long *)(hd + hl.dom_pref);
-    bv.asc_pref = (const long long *)(hd + hl.asc_pref);
+    bv.tab = (CInst *)(hd + hl.tab);
+    bv.pt_pref = (const NSGA3_RO int *)(hd + hl.pt_pref);
+    bv.ref_pref = (const NSGA3_RO int *)(hd + hl.ref_pref);
+    bv.chunk_pref = (const NSGA3_RO int *)(hd + hl.chunk_pref);
+    bv.tile_pref = (const NSGA3_RO int *)(hd + hl.tile_pref);
+    bv.order = (const NSGA3_RO int *)(hd + hl.order);
+    bv.dom_pref = (const NSGA3_RO long long *)(hd + hl.dom_pref);
+    bv.asc_pref = (const NSGA3_RO long long *)(hd + hl.asc_pref);
     bv.ticket = (u64 *)(hd + hl.ticket);
     bv.B = B;
     bv.run = run;

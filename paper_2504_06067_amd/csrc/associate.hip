@@ -22,7 +22,7 @@ namespace nsga3 {
 
 __global__ __launch_bounds__(256) void k_assoc_list(BatchView bv) {
     const Local L = locate(bv.pt_pref, bv.B);
-    const Inst &I = bv.tab[L.b];
+    CInst &I = bv.tab[L.b];
     const int t = L.i;
     const int l = I.front_info[0];
     const bool in = t < I.M && I.rank[t] >= 0 && I.rank[t] <= l;
@@ -42,7 +42,7 @@ __global__ __launch_bounds__(256) void k_assoc_list(BatchView bv) {
 }
 
 template <int MO>
-__device__ __forceinline__ void assoc_ref(const float (&f)[MO], const float *__restrict__ wn,
+__device__ __forceinline__ void assoc_ref(const float (&f)[MO], const NSGA3_RO float *wn,
                                           int Hp, int j, float &best, int &bj) {
     float w[MO];
 #pragma unroll
@@ -70,7 +70,7 @@ __global__ __launch_bounds__(256) void k_associate(BatchView bv, int gs, int gn,
     const long long gitem = uniform(item0 + (long long)blockIdx.x * 4 + (threadIdx.x >> 6));
     if (gitem >= item0 + n_items) return;
     const int gi = uniform(find_range(bv.asc_pref + gs, gn, gitem));
-    const Inst &I = bv.tab[bv.order[gs + gi]];
+    CInst &I = bv.tab[bv.order[gs + gi]];
     const long long item = gitem - bv.asc_pref[gs + gi];
     const int n = I.P.ctrl->list_count;
     const int pb = (int)(item / I.nslice);
@@ -80,7 +80,8 @@ __global__ __launch_bounds__(256) void k_associate(BatchView bv, int gs, int gn,
     const bool in = i < n;
     const int x = in ? I.P.list[i] : I.P.list[pb * 64];
     const float *__restrict__ Fn = I.Fn;
-    const float *__restrict__ wn = I.P.wn;
+    // unit directions: written by k_prep, read-only here (invariant loads)
+    const NSGA3_RO float *wn = (const NSGA3_RO float *)I.P.wn;
     const int H = I.H, Hp = I.Hp;
     float f[MO];
 #pragma unroll
@@ -105,7 +106,7 @@ __global__ __launch_bounds__(256) void k_associate(BatchView bv, int gs, int gn,
 
 __global__ __launch_bounds__(256) void k_assoc_final(BatchView bv) {
     const Local L = locate(bv.pt_pref, bv.B);
-    const Inst &I = bv.tab[L.b];
+    CInst &I = bv.tab[L.b];
     Ctrl *ctrl = I.P.ctrl;
     const int n = ctrl->list_count;
     if (L.i >= n) return;

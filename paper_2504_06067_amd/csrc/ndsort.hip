@@ -26,7 +26,7 @@ long long dominance_items(int W, int G_) {
 }
 
 __global__ __launch_bounds__(256) void k_init(BatchView bv) {
-    const Inst &I = bv.tab[blockIdx.x];
+    CInst &I = bv.tab[blockIdx.x];
     Ctrl *ctrl = I.P.ctrl;
     const int t = threadIdx.x;
     if (t == 0) {
@@ -55,7 +55,7 @@ __global__ __launch_bounds__(256) void k_prep(BatchView bv, int npt) {
     const bool points = (int)(blockIdx.x * blockDim.x) < npt;
     if (points) {
         const Local L = locate(bv.pt_pref, bv.B);
-        const Inst &I = bv.tab[L.b];
+        CInst &I = bv.tab[L.b];
         const int j = L.i, M = I.M, m = I.m, Mp = I.Mp;
         bool bad = false;
         if (j < Mp && (bv.run & RUN_ND)) {
@@ -80,7 +80,7 @@ __global__ __launch_bounds__(256) void k_prep(BatchView bv, int npt) {
     } else {
         const int base = uniform((int)(blockIdx.x * blockDim.x)) - npt;
         const int b = uniform(find_range(bv.ref_pref, bv.B, base));
-        const Inst &I = bv.tab[b];
+        CInst &I = bv.tab[b];
         const int t = base - bv.ref_pref[b] + (int)threadIdx.x;
         const int H = I.H, Hp = I.Hp, m = I.m;
         bool bad = false;
@@ -122,26 +122,38 @@ __device__ __forceinline__ unsigned write_lane(unsigned old, unsigned v) {
     return old;
 }
 
-__device__ __forceinline__ long long items_before(long long jb, long long G) {
-    const long long q = jb / G, s = jb % G;
-    return jb + G * q * (q - 1) / 2 + q * s;
+// Work items of block rows 0 .. jb - 1 for G = 2^gsh column tiles per item.
+__device__ __forceinline__ long long items_before(int jb, int gsh) {
+    const long long q = jb >> gsh, s = jb & ((1 << gsh) - 1);
+    return (long long)jb + (((q * (q - 1)) >> 1) << gsh) + q * s;
 }
 
-// One compare step against column point i = 64 * ib + R (uniform): the wave
-// masks lt = {j : f_i < f_j in some objective}, gt = {j : f_i > f_j in some
-// objective} come from 2m compares; then
+// GW consecutive column values of one objective (one scalar load). The
+// group width keeps GW * m values within the scalar register budget.
+template <int MO>
+constexpr int col_group() { return MO <= 4 ? 8 : (MO <= 8 ? 4 : 2); }
+
+template <int GW>
+struct alignas(4 * GW) ColV {
+    float a[GW];
+};
+
+// One compare step against column point i = 64 * ib + R (uniform, objective
+// values v[k].a[R % GW]): the wave masks lt = {j : f_i < f_j in some
+// objective}, gt = {j : f_i > f_j in some objective} come from 2m compares;
+// then
 //   i dominates j  <=>  j in lt \ gt   (bit R of lane j's word A)
 //   j dominates i  <=>  j in gt \ lt   (the whole mask is row i's word B)
-template <int MO, int R>
-__device__ __forceinline__ void dom_step(const float *__restrict__ fi, const float (&fj)[MO],
+template <int MO, int GW, int R>
+__device__ __forceinline__ void dom_step(const ColV<GW> (&v)[MO], const float (&fj)[MO],
                                          unsigned &a_lo, unsigned &a_hi, unsigned &b_lo,
                                          unsigned &b_hi) {
     u64 lt = 0, gt = 0;
 #pragma unroll
     for (int k = 0; k < MO; ++k) {
-        const float v = fi[k * 64 + R];
-        lt |= ballot(v < fj[k]);
-        gt |= ballot(v > fj[k]);
+        const float x = v[k].a[R % GW];
+        lt |= ballot(x < fj[k]);
+        gt |= ballot(x > fj[k]);
     }
     const u64 i_dom_j = lt & ~gt;
     const u64 j_dom_i = gt & ~lt;
@@ -151,14 +163,34 @@ __device__ __forceinline__ void dom_step(const float *__restrict__ fi, const flo
     b_hi = write_lane<R>(b_hi, (unsigned)(j_dom_i >> 32));
 }
 
+// Column points GW*g + GW - 1 down to GW*g: their values arrive with one
+// scalar load per objective.
+template <int MO, int GW, int g, int... Is>
+__device__ __forceinline__ void dom_group(std::integer_sequence<int, Is...>,
+                                          const NSGA3_RO float *fi, const float (&fj)[MO],
+                                          unsigned &a_lo, unsigned &a_hi, unsigned &b_lo,
+                                          unsigned &b_hi) {
+    ColV<GW> v[MO];
+#pragma unroll
+    for (int k = 0; k < MO; ++k) {
+        const NSGA3_RO ColV<GW> &src = *(const NSGA3_RO ColV<GW> *)(fi + k * 64 + GW * g);
+#pragma unroll
+        for (int q = 0; q < GW; ++q) v[k].a[q] = src.a[q];
+    }
+    (dom_step<MO, GW, GW * g + GW - 1 - Is>(v, fj, a_lo, a_hi, b_lo, b_hi), ...);
+}
+
 // R runs 63 down to 0 so that the shifted-in bit of point 64*ib + R lands at
 // bit R (of the high word for R >= 32).
-template <int MO, int... Is>
-__device__ __forceinline__ void dom_tile(std::integer_sequence<int, Is...>,
-                                         const float *__restrict__ fi, const float (&fj)[MO],
+template <int MO, int GW, int... Gs>
+__device__ __forceinline__ void dom_tile(std::integer_sequence<int, Gs...>,
+                                         const NSGA3_RO float *fi, const float (&fj)[MO],
                                          unsigned &a_lo, unsigned &a_hi, unsigned &b_lo,
                                          unsigned &b_hi) {
-    (dom_step<MO, 63 - Is>(fi, fj, a_lo, a_hi, b_lo, b_hi), ...);
+    constexpr int NG = 64 / GW;
+    (dom_group<MO, GW, NG - 1 - Gs>(std::make_integer_sequence<int, GW>{}, fi, fj, a_lo, a_hi,
+                                    b_lo, b_hi),
+     ...);
 }
 
 // One wave per work item of the instances with m = MO (the group order[gs ..
@@ -172,21 +204,23 @@ __global__ __launch_bounds__(256) void k_dominance(BatchView bv, int gs, int gn,
     const long long gitem = uniform(item0 + (long long)blockIdx.x * 4 + (threadIdx.x >> 6));
     if (gitem >= item0 + n_items) return;
     const int gi = uniform(find_range(bv.dom_pref + gs, gn, gitem));
-    const Inst &I = bv.tab[bv.order[gs + gi]];
+    CInst &I = bv.tab[bv.order[gs + gi]];
     const long long item = gitem - bv.dom_pref[gs + gi];
-    const int W = I.W, Mp = I.Mp, G = I.G;
-    const float *__restrict__ ft = I.P.ft;
+    const int W = I.W, Mp = I.Mp, G = I.G, gsh = __builtin_ctz((unsigned)G);
+    // the objective copy is written by k_prep and only read here: invariant
+    // loads, so the column points come through the scalar cache
+    const NSGA3_RO float *ft = (const NSGA3_RO float *)I.P.ft;
     u64 *__restrict__ mask = I.P.mask;
     int *__restrict__ nd = I.P.nd;
     // block row: largest jb with items_before(jb) <= item
     int lo = 0, hi = W;
     while (hi - lo > 1) {
         const int mid = (lo + hi) >> 1;
-        if (items_before(mid, G) <= item) lo = mid;
+        if (items_before(mid, gsh) <= item) lo = mid;
         else hi = mid;
     }
     const int jb = lo;
-    const int g = (int)(item - items_before(jb, G));
+    const int g = (int)(item - items_before(jb, gsh));
     const int ib0 = g * G;
     const int ib1 = min(ib0 + G, jb + 1);
 
@@ -198,8 +232,9 @@ __global__ __launch_bounds__(256) void k_dominance(BatchView bv, int gs, int gn,
     int cnt_j = 0;
     for (int ib = ib0; ib < ib1; ++ib) {
         unsigned a_lo = 0, a_hi = 0, b_lo = 0, b_hi = 0;
-        const float *fi = (const float *)__builtin_assume_aligned(ft + (size_t)ib * MO * 64, 256);
-        dom_tile<MO>(std::make_integer_sequence<int, 64>{}, fi, fj, a_lo, a_hi, b_lo, b_hi);
+        const NSGA3_RO float *fi = ft + (size_t)ib * MO * 64;
+        constexpr int GW = col_group<MO>();
+        dom_tile<MO, GW>(std::make_integer_sequence<int, 64 / GW>{}, fi, fj, a_lo, a_hi, b_lo, b_hi);
         const u64 A = ((u64)a_hi << 32) | a_lo;
         mask[(size_t)ib * Mp + jglob] = A;
         cnt_j += __popcll(A);
@@ -284,7 +319,7 @@ struct PeelShared {
 
 // Row-major copy of chunk c's rows: rowm[j][w] = mask[w][j], through a
 // padded 64 x 64-word LDS tile (coalesced reads and writes).
-__device__ void peel_transpose(const Inst &I, int c, PeelShared &sh) {
+__device__ void peel_transpose(CInst &I, int c, PeelShared &sh) {
     const int lane = lane_id();
     const int wv = uniform((int)(threadIdx.x >> 6));
     const int W = I.W, Mp = I.Mp;
@@ -311,7 +346,11 @@ __device__ void peel_transpose(const Inst &I, int c, PeelShared &sh) {
 
 // Ranks the points of chunk c that are alive at front k and have no alive
 // dominator; publishes the chunk's result. All waves take part.
-__device__ void peel_chunk(const Inst &I, int k, int c, PeelShared &sh) {
+// STAGED: the alive words of front k are copied to LDS (W <= PEEL_LDS_ALIVE);
+// a compile-time choice, so that no pointer ever selects between LDS and
+// global memory.
+template <bool STAGED>
+__device__ void peel_chunk_impl(CInst &I, int k, int c, PeelShared &sh) {
     const int lane = lane_id();
     const int wv = uniform((int)(threadIdx.x >> 6));
     const int W = I.W, ns = I.ns;
@@ -323,7 +362,7 @@ __device__ void peel_chunk(const Inst &I, int k, int c, PeelShared &sh) {
     if (k == 0) {
         newly = aw & ballot(I.P.nd[j] == 0);
     } else {
-        const bool staged = W <= PEEL_LDS_ALIVE;
+        constexpr bool staged = STAGED;
         const u64 *__restrict__ rowm = I.P.rowm;
         int *wit = I.P.wit;
         __syncthreads();  // the previous chunk is done with the shared words
@@ -425,6 +464,11 @@ __device__ void peel_chunk(const Inst &I, int k, int c, PeelShared &sh) {
     }
 }
 
+__device__ __forceinline__ void peel_chunk(CInst &I, int k, int c, PeelShared &sh) {
+    if (uniform(I.W) <= PEEL_LDS_ALIVE) peel_chunk_impl<true>(I, k, c, sh);
+    else peel_chunk_impl<false>(I, k, c, sh);
+}
+
 __global__ __launch_bounds__(64 * PEEL_WAVES) void k_peel(BatchView bv, int nchunk) {
     __shared__ PeelShared sh;
     const int lane = lane_id();
@@ -464,7 +508,7 @@ __global__ __launch_bounds__(64 * PEEL_WAVES) void k_peel(BatchView bv, int nchu
             const int c = uniform(sh.own_c[q]);
             const int cum_prev = uniform(sh.own_cum[q]);
             if (cum_prev < 0) continue;  // this instance finished
-            const Inst &I = bv.tab[b];
+            CInst &I = bv.tab[b];
             // wait for front k - 1 of the instance
             if (wv == 0) {
                 const u64 *slot = peel_slot(I.P.facc, k - 1);

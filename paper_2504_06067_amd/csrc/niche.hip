@@ -36,7 +36,7 @@ constexpr int TILE = COMPACT_TILE;      // compaction tile
 // Stage call only (a whole selection counts in the association's final pass).
 __global__ __launch_bounds__(256) void k_niche_count(BatchView bv) {
     const Local L = locate(bv.pt_pref, bv.B);
-    const Inst &I = bv.tab[L.b];
+    CInst &I = bv.tab[L.b];
     const int x = L.i;
     if (x >= I.M) return;
     const int l = I.front_info[0];
@@ -78,7 +78,7 @@ __device__ __forceinline__ long long block_max_ll(long long v, long long *red) {
 
 // One workgroup per instance.
 __global__ __launch_bounds__(PLAN_THREADS) void k_niche_plan(BatchView bv) {
-    const Inst &I = bv.tab[blockIdx.x];
+    CInst &I = bv.tab[blockIdx.x];
     const int *__restrict__ rho = I.P.rho;
     const int *__restrict__ cnt = I.P.cnt;
     const int H = I.H;
@@ -267,7 +267,7 @@ __global__ __launch_bounds__(PLAN_THREADS) void k_niche_plan(BatchView bv) {
 
 __global__ __launch_bounds__(256) void k_niche_scatter(BatchView bv) {
     const Local L = locate(bv.pt_pref, bv.B);
-    const Inst &I = bv.tab[L.b];
+    CInst &I = bv.tab[L.b];
     const int x = L.i;
     if (x >= I.M) return;
     if (I.rank[x] != I.front_info[0]) return;
@@ -340,7 +340,7 @@ __global__ __launch_bounds__(256) void k_niche_pick(BatchView bv) {
     __shared__ u64 s_rem[4][PICK_CAP / 64];
     const int base = uniform((int)(blockIdx.x * 4));
     const int b = uniform(find_range(bv.ref_pref, bv.B, base));
-    const Inst &I = bv.tab[b];
+    CInst &I = bv.tab[b];
     const int *__restrict__ rho = I.P.rho;
     const int *__restrict__ cnt = I.P.cnt;
     const int *__restrict__ off = I.P.off;
@@ -442,7 +442,7 @@ __global__ __launch_bounds__(256) void k_niche_pick(BatchView bv) {
 __global__ __launch_bounds__(256) void k_compact_count(BatchView bv) {
     __shared__ long long red[4];
     const int b = uniform(find_range(bv.tile_pref, bv.B, (int)blockIdx.x));
-    const Inst &I = bv.tab[b];
+    CInst &I = bv.tab[b];
     const int l = I.front_info[0];
     const int M = I.M;
     const int tile = (int)blockIdx.x - bv.tile_pref[b];
@@ -463,7 +463,7 @@ __global__ __launch_bounds__(256) void k_compact_write(BatchView bv) {
     __shared__ long long red[4];
     __shared__ int wsum[4];
     const int b = uniform(find_range(bv.tile_pref, bv.B, (int)blockIdx.x));
-    const Inst &I = bv.tab[b];
+    CInst &I = bv.tab[b];
     const int l = I.front_info[0];
     const int M = I.M, N = I.N;
     const int tile = (int)blockIdx.x - bv.tile_pref[b];

@@ -18,7 +18,7 @@ namespace nsga3 {
 
 __global__ __launch_bounds__(256) void k_norm_reduce(BatchView bv) {
     const Local L = locate(bv.pt_pref, bv.B);
-    const Inst &I = bv.tab[L.b];
+    CInst &I = bv.tab[L.b];
     const int x = L.i, M = I.M, m = I.m;
     Ctrl *ctrl = I.P.ctrl;
     const int l = I.front_info[0];
@@ -56,7 +56,7 @@ template <int MO>
 __global__ __launch_bounds__(256) void k_norm_extreme(BatchView bv, int gs, int gn, int pt0) {
     const int base = uniform(pt0 + (int)(blockIdx.x * blockDim.x));
     const int gi = uniform(find_range(bv.pt_pref, bv.B, base));
-    const Inst &I = bv.tab[gi];
+    CInst &I = bv.tab[gi];
     Ctrl *ctrl = I.P.ctrl;
     const int n = ctrl->list_count;
     const int i = base - bv.pt_pref[gi] + (int)threadIdx.x;
@@ -94,7 +94,7 @@ __global__ __launch_bounds__(256) void k_norm_extreme(BatchView bv, int gs, int 
 // in FP64; solve E b = 1 by Gaussian elimination with partial pivoting
 // (largest |pivot|, least row on ties); a_k = 1 / b_k unless degenerate.
 __global__ void k_norm_solve(BatchView bv) {
-    const Inst &I = bv.tab[blockIdx.x];
+    CInst &I = bv.tab[blockIdx.x];
     if (threadIdx.x != 0) return;
     Ctrl *ctrl = I.P.ctrl;
     const int M = I.M, m = I.m;
@@ -160,7 +160,7 @@ __global__ void k_norm_solve(BatchView bv) {
 
 __global__ __launch_bounds__(256) void k_norm_apply(BatchView bv) {
     const Local L = locate(bv.pt_pref, bv.B);
-    const Inst &I = bv.tab[L.b];
+    CInst &I = bv.tab[L.b];
     const Ctrl *ctrl = I.P.ctrl;
     const int n = ctrl->list_count;
     if (L.i >= n) return;

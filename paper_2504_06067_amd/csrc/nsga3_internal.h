@@ -121,19 +121,26 @@ struct Inst {
     int ntiles;         // compaction tiles
 };
 
+// Descriptor memory (the batch header) is written by a call's first kernels
+// and only read by every later kernel of the call. Reads through this
+// address space are invariant loads, which the compiler may keep in
+// registers or repeat across barriers, fences and atomics.
+#define NSGA3_RO __attribute__((address_space(4)))
+typedef const NSGA3_RO Inst CInst;
+
 // Global index ranges: instance b owns [pref[b], pref[b+1]) of each kind.
 // Point and reference ranges are padded to PT_ALIGN so that no 256-thread
 // block straddles two instances. dom_pref / asc_pref run over `order`
 // (instances sorted by m) and count per-wave work items.
 struct BatchView {
-    const Inst *tab;
-    const int *pt_pref;
-    const int *ref_pref;
-    const int *chunk_pref;
-    const int *tile_pref;
-    const int *order;
-    const long long *dom_pref;
-    const long long *asc_pref;
+    CInst *tab;
+    const NSGA3_RO int *pt_pref;
+    const NSGA3_RO int *ref_pref;
+    const NSGA3_RO int *chunk_pref;
+    const NSGA3_RO int *tile_pref;
+    const NSGA3_RO int *order;
+    const NSGA3_RO long long *dom_pref;
+    const NSGA3_RO long long *asc_pref;
     u64 *ticket;        // batch-level peel ticket counter
     int B;
     int run;            // RUN_* flags of this call
@@ -143,7 +150,7 @@ struct BatchView {
 
 // Largest b in [0, n) with pref[b] <= x (pref[0] <= x < pref[n]).
 template <typename T>
-__device__ __forceinline__ int find_range(const T *pref, int n, T x) {
+__device__ __forceinline__ int find_range(const NSGA3_RO T *pref, int n, T x) {
     int lo = 0, hi = n;
     while (hi - lo > 1) {
         const int mid = (lo + hi) >> 1;
@@ -262,7 +269,7 @@ struct Local {
     int b;      // instance
     int i;      // local index of this thread
 };
-__device__ __forceinline__ Local locate(const int *pref, int B) {
+__device__ __forceinline__ Local locate(const NSGA3_RO int *pref, int B) {
     const int base = uniform((int)(blockIdx.x * blockDim.x));
     const int b = uniform(find_range(pref, B, base));
     return Local{b, base - pref[b] + (int)threadIdx.x};
