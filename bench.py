@@ -42,6 +42,14 @@ def parse():
     ap.add_argument("--batched-reps", type=int, default=20)
     ap.add_argument("--only-batched", action="store_true",
                     help="run the batched comparison alone (for profiling it separately)")
+    ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--only-served", action="store_true",
+                    help="run the served comparison alone (for profiling it separately)")
+    ap.add_argument("--served-requests", type=int, default=64)
+    ap.add_argument("--served-generations", type=int, default=50)
+    ap.add_argument("--served-budget-gb", type=float, default=64.0)
+    ap.add_argument("--served-load", type=float, default=0.8,
+                    help="offered load as a fraction of the plain loop's capacity")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target CPU time of the oracle sample")
     return ap.parse_args()
@@ -156,6 +164,60 @@ def bench_batched(args, dev):
     }
 
 
+def bench_served(args, dev):
+    """Resident runs (50 generations each) arriving as a Poisson stream:
+    the continuous-batching server against the plain loop that serves one
+    request at a time with plain calls, on the same trace. The offered load
+    is a fraction of the plain loop's capacity, measured first by running
+    the requests back to back."""
+    import numpy as np
+
+    from paper_2504_06067_amd import serve, workloads
+
+    R, G = args.served_requests, args.served_generations
+    budget = int(args.served_budget_gb * (1 << 30))
+    calib = workloads.served_trace(args.seed, R, qps=1.0, generations=G)
+    t_cal = serve.Server(dev, budget=budget, mode="plain").run(calib, realtime=False)
+    mu = R / t_cal[None]["makespan_s"]
+    qps = args.served_load * mu
+    trace = workloads.served_trace(args.seed, R, qps=qps, generations=G)
+    work = sum(q["M"] * G for q in trace)
+    out = {}
+    results = {}
+    for mode in ("batched", "plain"):
+        r = serve.Server(dev, budget=budget, mode=mode).run(trace, realtime=True)
+        results[mode] = r
+        lat = np.array([r[q["rid"]]["latency_s"] for q in trace])
+        bad = [q["rid"] for q in trace if r[q["rid"]]["status"] != 0]
+        if bad:
+            raise RuntimeError(f"served status not OK for requests {bad[:5]}")
+        span = r[None]["makespan_s"]
+        out[mode] = {"latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3),
+                                    "p99": float(np.percentile(lat, 99) * 1e3),
+                                    "mean": float(lat.mean() * 1e3)},
+                     "makespan_s": span, "value": work / span, "ticks": r[None]["ticks"],
+                     "peak_active": r[None]["peak_active"],
+                     "peak_pool_gb": r[None]["peak_pool_bytes"] / (1 << 30)}
+    same = all(np.array_equal(results["batched"][q["rid"]]["X"], results["plain"][q["rid"]]["X"])
+               and np.array_equal(results["batched"][q["rid"]]["F"],
+                                  results["plain"][q["rid"]]["F"]) for q in trace)
+    return {
+        "workload": f"{R} requests, Poisson arrivals, 2N log-uniform [1000, 100000], m in "
+                    f"{{3,5,10,15}}, d=12, {G} generations each (SBX + polynomial mutation + "
+                    f"synthetic objective map, then selection)",
+        "unit": "merged solutions selected/s (sum of 2N x generations / makespan)",
+        "plain_capacity_rps": mu,
+        "qps": qps,
+        "load": args.served_load,
+        "hbm_budget_gb": args.served_budget_gb,
+        "served": out["batched"],
+        "plain": out["plain"],
+        "speedup_p50": out["plain"]["latency_ms"]["p50"] / out["batched"]["latency_ms"]["p50"],
+        "speedup_p99": out["plain"]["latency_ms"]["p99"] / out["batched"]["latency_ms"]["p99"],
+        "results_identical": bool(same),
+    }
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -171,6 +233,9 @@ def main():
     dev = torch.device("cuda:0")
     if args.only_batched:
         print(json.dumps({"batched": bench_batched(args, dev)}), flush=True)
+        return
+    if args.only_served:
+        print(json.dumps({"served": bench_served(args, dev)}), flush=True)
         return
     inst = workloads.plain_instance(args.workload, args.seed)
     M, m, H, N = inst["M"], inst["m"], inst["H"], inst["N"]
@@ -244,6 +309,8 @@ def main():
     }
     if not args.no_batched:
         res["batched"] = bench_batched(args, dev)
+    if not args.no_served:
+        res["served"] = bench_served(args, dev)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(inst, args.cpu_seconds)
     print(json.dumps(res), flush=True)

@@ -160,13 +160,22 @@ typedef struct nsga3_instance {
     uint64_t seed;        /* tie-break seed, as nsga3_select */
     int32_t tile[4];      /* tile parameters, 0 = automatic: [0] column tiles of 64
                            * points per dominance work item (a power of two, 1..64),
-                           * [1] references
-                           * per association slice (16..H, multiple of 16 unless H);
-                           * [2], [3] must be 0. Results do not depend on them. */
+                           * [1] references per association slice (16..H, a multiple
+                           * of 16, or H); [2], [3] must be 0. Results do not depend
+                           * on them. */
+    void *ws;             /* this instance's own workspace region (256-byte aligned,
+                           * at least nsga3_instance_workspace_bytes), or NULL: the
+                           * region is carved from the call's workspace */
+    size_t ws_bytes;      /* size of `ws` */
 } nsga3_instance;
 
-/* Workspace bytes for a batch of B instances [host array]; 0 if any instance
- * or B (1..NSGA3_MAX_BATCH) would be rejected. Pure host function. */
+/* Workspace bytes of one instance's own region (nsga3_instance.ws); 0 for a
+ * shape every call would reject. Pure host function. */
+size_t nsga3_instance_workspace_bytes(int32_t M, int32_t m, int32_t H, int32_t N);
+
+/* Workspace bytes of a batched call [host array]: the batch header plus the
+ * regions of the instances whose ws is NULL; 0 if any instance or B
+ * (1..NSGA3_MAX_BATCH) would be rejected. Pure host function. */
 size_t nsga3_batched_workspace_bytes(const nsga3_instance *inst, int32_t B);
 
 /* nsga3_select for every instance of inst[0..B) [host array]. Instances must
@@ -178,9 +187,59 @@ int nsga3_select_batched(const nsga3_instance *inst, int32_t B, void *ws, size_t
 
 /* Waits for `stream`, then reads the status of every instance of the last
  * batched call on `ws` into status[0..B) [host], each as nsga3_read_status.
- * `inst` and B must be those of that call. */
+ * `inst` and B must be those of that call. (An instance with its own region
+ * keeps its status at the start of that region: nsga3_read_status(inst.ws)
+ * reads it alone.) */
 int nsga3_read_status_batched(const nsga3_instance *inst, int32_t B, const void *ws,
                               void *stream, int32_t *status);
+
+/* ------------------------------------------------------ generation step
+ * The step that a served run repeats between selections (Sec. II-C: mating
+ * and the variation operators SBX and polynomial mutation produce n
+ * offspring; Algorithm 1, "Crossover+Mutation"), for a batch of resident
+ * populations, with a synthetic objective map. Not part of the selection.
+ * Per slot, decision vectors are row-major float32 [rows][d] in [0, 1),
+ * objectives [rows][m]:
+ *   NSGA3_EVOLVE_INIT        rows 0..N-1 of X_new/F_new: a uniform random
+ *                            population and its objectives (X_old, F_old,
+ *                            sel unused)
+ *   NSGA3_EVOLVE_POPULATION  rows 0..N-1: the population, row r taken from
+ *                            row sel[r] of X_old/F_old (sel NULL: row r)
+ *   NSGA3_EVOLVE_GENERATION  the population as above, then N offspring in
+ *                            rows N..2N-1: random mating pairs, SBX with
+ *                            distribution index 20 on every variable, then
+ *                            polynomial mutation (rate 1/d, index 20), values
+ *                            clamped to [0, 1 - 2^-24]; F_new = f(X_new)
+ * Objective map: y = A (x_1..x_{d-1} - 1/2), u = |y| / ||y||,
+ * f = u (1 - 0.3 ln(1 - x_d)). Random draws are SplitMix64 hashes of
+ * (seed, generation, individual, variable): a population evolves the same
+ * alone or batched. X_new/F_new must not overlap X_old/F_old. */
+#define NSGA3_EVOLVE_GENERATION 0
+#define NSGA3_EVOLVE_POPULATION 1
+#define NSGA3_EVOLVE_INIT 2
+#define NSGA3_MAX_DECISION 64
+
+typedef struct nsga3_evolve_slot {
+    const float *X_old;   /* [*][d] previous merged decision vectors (read) */
+    const int32_t *sel;   /* [N] population rows of X_old/F_old, or NULL (read) */
+    const float *F_old;   /* [*][m] their objectives (read) */
+    float *X_new;         /* [2N][d] (GENERATION) or [N][d] (write) */
+    float *F_new;         /* [2N][m] or [N][m] (write) */
+    const float *A;       /* [m][d-1] objective map matrix (read) */
+    int32_t N, d, m;      /* N in [1, 2^19], d in [2, NSGA3_MAX_DECISION], m in [2, 16] */
+    int32_t generation;   /* in [0, 65535] */
+    uint64_t seed;
+    int32_t mode;         /* NSGA3_EVOLVE_* */
+    int32_t reserved;     /* must be 0 */
+} nsga3_evolve_slot;
+
+/* Workspace bytes of a generation step over B slots (descriptor table). */
+size_t nsga3_evolve_workspace_bytes(int32_t B);
+
+/* One generation step for slots[0..B) [host array], B in 1..NSGA3_MAX_BATCH.
+ * Returns NSGA3_EINVAL (nothing enqueued) for a bad slot. */
+int nsga3_evolve_batched(const nsga3_evolve_slot *slots, int32_t B, void *ws, size_t ws_bytes,
+                         void *stream);
 
 /* Waits for `stream`, then reads the status word of `ws` into *status [host]
  * (NSGA3_OK, NSGA3_ENONFINITE, NSGA3_EINVAL or NSGA3_EINTERNAL). Returns

@@ -141,6 +141,12 @@ static HeaderLayout header_layout(int B) {
 // batch whole reference sets per wave).
 constexpr long long ASSOC_WAVES = 16384;
 
+// Column tiles per dominance work item when the caller does not choose:
+// small groups balance the triangle's uneven rows better; from about 400
+// words per row on, four tiles amortize each item's setup (measured on the
+// large and many-objective workloads).
+static int dominance_group(int W) { return W <= 400 ? 2 : 4; }
+
 static int auto_slice(int H, long long sum_W) {
     long long R = (long long)H * sum_W / ASSOC_WAVES;
     R = ((R + 15) / 16) * 16;
@@ -153,6 +159,8 @@ static int auto_slice(int H, long long sum_W) {
 struct Spec {
     Inst I;     // caller pointers and shape; P filled by plan()
     int tile[4];
+    char *own;  // the instance's own workspace region, or null
+    size_t own_bytes;
 };
 
 // Copies 4-byte words of the batch header from the kernel arguments.
@@ -169,7 +177,8 @@ __global__ __launch_bounds__(256) void k_blob(Blob b, unsigned *dst, int n) {
 // the device view.
 struct Plan {
     std::vector<Layout> lay;
-    std::vector<size_t> region;
+    std::vector<size_t> region;   // offset in the call's workspace (own regions: unused)
+    std::vector<char *> base;     // start of each instance's region
     size_t inst_total = 0;
     HeaderLayout hl;
     size_t total = 0;
@@ -196,13 +205,15 @@ static void plan(std::vector<Spec> &spec, char *ws, int run, Plan &p) {
         const Inst &I = spec[b].I;
         p.lay[b] = make_layout(I.M, I.m, I.H, I.N);
         p.region[b] = o;
-        o += p.lay[b].total;
+        if (!spec[b].own) o += p.lay[b].total;
         sum_W += p.lay[b].W;
     }
     p.inst_total = o;
     p.hl = header_layout(B);
     p.total = o + p.hl.total;
     if (!ws) return;
+    p.base.resize(B);
+    for (int b = 0; b < B; ++b) p.base[b] = spec[b].own ? spec[b].own : ws + p.region[b];
 
     std::vector<Inst> tab(B);
     std::vector<int> pt(B + 1), ref(B + 1), chunk(B + 1), tile(B + 1), order(B);
@@ -211,12 +222,12 @@ static void plan(std::vector<Spec> &spec, char *ws, int run, Plan &p) {
     for (int b = 0; b < B; ++b) {
         const Layout &L = p.lay[b];
         Inst I = spec[b].I;
-        I.P = carve(L, ws + p.region[b]);
+        I.P = carve(L, p.base[b]);
         I.Mp = L.Mp;
         I.W = L.W;
         I.Hp = L.Hp;
         I.ns = L.ns;
-        I.G = spec[b].tile[0] > 0 ? spec[b].tile[0] : DOM_G_DEFAULT;
+        I.G = spec[b].tile[0] > 0 ? spec[b].tile[0] : dominance_group(L.W);
         I.R = spec[b].tile[1] > 0 ? spec[b].tile[1] : auto_slice(I.H, sum_W);
         I.nslice = (I.H + I.R - 1) / I.R;
         I.ntiles = (I.M + COMPACT_TILE - 1) / COMPACT_TILE;
@@ -283,18 +294,23 @@ static void plan(std::vector<Spec> &spec, char *ws, int run, Plan &p) {
     bv.run = run;
 }
 
-// Enqueues the header copy, then the stages of `run`.
-static hipError_t enqueue(Plan &p, char *ws, hipStream_t s) {
-    unsigned *dst = (unsigned *)(ws + p.inst_total);
-    const unsigned *src = (const unsigned *)p.hdr.data();
-    const int words = (int)(p.hdr.size() / 4);
+hipError_t upload(const void *src_, size_t bytes, void *dst_, hipStream_t s) {
+    unsigned *dst = (unsigned *)dst_;
+    const unsigned *src = (const unsigned *)src_;
+    const int words = (int)(bytes / 4);
     Blob blob;
     for (int w0 = 0; w0 < words; w0 += BLOB_WORDS) {
         const int n = std::min(BLOB_WORDS, words - w0);
         memcpy(blob.w, src + w0, (size_t)n * 4);
         NSGA3_LAUNCH("header", k_blob, dim3(1), dim3(256), 0, s, blob, dst + w0, n);
     }
-    hipError_t e = launch_prepare(p.hp, p.bv, s);
+    return hipGetLastError();
+}
+
+// Enqueues the header copy, then the stages of `run`.
+static hipError_t enqueue(Plan &p, char *ws, hipStream_t s) {
+    hipError_t e = upload(p.hdr.data(), p.hdr.size(), ws + p.inst_total, s);
+    if (e == hipSuccess) e = launch_prepare(p.hp, p.bv, s);
     const int run = p.bv.run;
     if (e == hipSuccess && (run & RUN_ND)) e = launch_nd_sort(p.hp, p.bv, s);
     if (e == hipSuccess && (run & RUN_NORM)) e = launch_normalize(p.hp, p.bv, s);
@@ -351,6 +367,8 @@ static void specs_of(const nsga3_instance *inst, int B, std::vector<Spec> &v) {
         v[b].I.dist = q.dist;
         v[b].I.seed = q.seed;
         for (int t = 0; t < 4; ++t) v[b].tile[t] = q.tile[t];
+        v[b].own = (char *)q.ws;
+        v[b].own_bytes = q.ws_bytes;
     }
 }
 
@@ -358,7 +376,7 @@ static void specs_of(const nsga3_instance *inst, int B, std::vector<Spec> &v) {
 // instance's region; front_info, Fn and the normalization outputs always do.
 static void place_select(Plan &p, std::vector<Spec> &v, char *ws) {
     for (size_t b = 0; b < v.size(); ++b) {
-        const Ptrs P = carve(p.lay[b], ws + p.region[b]);
+        const Ptrs P = carve(p.lay[b], v[b].own ? v[b].own : ws + p.region[b]);
         Inst &I = v[b].I;
         if (!I.rank) I.rank = P.rank;
         if (!I.pi) I.pi = P.pi;
@@ -375,8 +393,10 @@ static void place_select(Plan &p, std::vector<Spec> &v, char *ws) {
 static int run_select(std::vector<Spec> &v, void *ws, size_t ws_bytes, hipStream_t s) {
     Plan p;
     plan(v, nullptr, RUN_SELECT, p);
-    const int rc = check_ws(p.total, ws, ws_bytes);
+    int rc = check_ws(p.total, ws, ws_bytes);
     if (rc) return rc;
+    for (size_t b = 0; b < v.size(); ++b)
+        if (v[b].own && (rc = check_ws(p.lay[b].total, v[b].own, v[b].own_bytes))) return rc;
     place_select(p, v, (char *)ws);
     plan(v, (char *)ws, RUN_SELECT, p);
     return to_status(enqueue(p, (char *)ws, s));
@@ -532,6 +552,35 @@ int nsga3_select(const float *F, int32_t M, int32_t m, const float *Z, int32_t H
     return run_select(v, ws, ws_bytes, (hipStream_t)stream);
 }
 
+size_t nsga3_instance_workspace_bytes(int32_t M, int32_t m, int32_t H, int32_t N) {
+    if (!valid_shape(M, m, H, N)) return 0;
+    return make_layout(M, m, H, N).total;
+}
+
+size_t nsga3_evolve_workspace_bytes(int32_t B) {
+    if (B < 1 || B > NSGA3_MAX_BATCH) return 0;
+    return evolve_header_bytes(B);
+}
+
+int nsga3_evolve_batched(const nsga3_evolve_slot *slots, int32_t B, void *ws, size_t ws_bytes,
+                         void *stream) {
+    if (!slots || B < 1 || B > NSGA3_MAX_BATCH) return NSGA3_EINVAL;
+    for (int b = 0; b < B; ++b) {
+        const nsga3_evolve_slot &q = slots[b];
+        const bool needs_old = q.mode != NSGA3_EVOLVE_INIT;
+        if (q.mode < NSGA3_EVOLVE_GENERATION || q.mode > NSGA3_EVOLVE_INIT || q.reserved != 0 ||
+            q.N < 1 || q.N > NSGA3_MAX_POINTS / 2 || q.d < 2 || q.d > NSGA3_MAX_DECISION ||
+            q.m < 2 || q.m > NSGA3_MAX_OBJECTIVES || q.generation < 0 ||
+            q.generation > 65535 || !q.X_new || !q.F_new || !q.A ||
+            (needs_old && (!q.X_old || !q.F_old)) || !aligned(q.X_new, 4) ||
+            !aligned(q.F_new, 4) || !aligned(q.A, 4))
+            return NSGA3_EINVAL;
+    }
+    const int rc = check_ws(evolve_header_bytes(B), ws, ws_bytes);
+    if (rc) return rc;
+    return to_status(launch_evolve(slots, B, (char *)ws, (hipStream_t)stream));
+}
+
 size_t nsga3_batched_workspace_bytes(const nsga3_instance *inst, int32_t B) {
     if (!inst || B < 1 || B > NSGA3_MAX_BATCH) return 0;
     for (int b = 0; b < B; ++b)
@@ -579,7 +628,8 @@ int nsga3_read_status_batched(const nsga3_instance *inst, int32_t B, const void 
     hipStream_t s = (hipStream_t)stream;
     std::vector<int> bits(B, 0);
     for (int b = 0; b < B; ++b) {
-        const Ctrl *ctrl = (const Ctrl *)((const char *)ws + p.region[b]);
+        const char *base = inst[b].ws ? (const char *)inst[b].ws : (const char *)ws + p.region[b];
+        const Ctrl *ctrl = (const Ctrl *)base;
         if (hipMemcpyAsync(&bits[b], &ctrl->status, sizeof(int), hipMemcpyDeviceToHost, s) !=
             hipSuccess)
             return NSGA3_EHIP;

@@ -115,6 +115,13 @@ __device__ __forceinline__ unsigned shift_in(unsigned a, u64 mask) {
     return r;
 }
 
+// The value of lane L (wave-uniform) of a 64-bit register pair.
+__device__ __forceinline__ u64 read_lane64(u64 x, int L) {
+    const unsigned lo = __builtin_amdgcn_readlane((unsigned)x, L);
+    const unsigned hi = __builtin_amdgcn_readlane((unsigned)(x >> 32), L);
+    return ((u64)hi << 32) | lo;
+}
+
 // Lane R of `old` takes the wave-uniform value v.
 template <int R>
 __device__ __forceinline__ unsigned write_lane(unsigned old, unsigned v) {
@@ -387,10 +394,9 @@ __device__ void peel_chunk_impl(CInst &I, int k, int c, PeelShared &sh) {
         __syncthreads();
         const u64 need = uniform(sh.need);
         // wave wv re-examines the needing points wv, wv + PEEL_WAVES, ... (lane
-        // order); the first 64-word round of all of them is issued at once
+        // order)
         constexpr int PER = 64 / PEEL_WAVES;
-        int pl[PER], wpos[PER];
-        u64 xr[PER];
+        int pl[PER];
         int mine = 0;
         {
             u64 rest = need;
@@ -404,51 +410,77 @@ __device__ void peel_chunk_impl(CInst &I, int k, int c, PeelShared &sh) {
                 }
             }
         }
+        // All needing points of the wave search together: each round loads the
+        // next 128 words (two per lane) of every point still searching, so the
+        // rounds of different points overlap instead of adding up.
+        int pos[PER], state[PER], fwi[PER];  // state: 0 searching, 1 found, 2 none, 3 unused
+        u64 fw[PER];
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
-            xr[q] = 0;
-            wpos[q] = 0;
+            pos[q] = 0;
+            fwi[q] = 0;
+            fw[q] = 0;
+            state[q] = q < mine ? 0 : 3;
             if (q < mine) {
-                const int jp = c * 64 + pl[q];
-                const int wp = uniform(wit[jp]);
-                wpos[q] = wp < 0 ? 0 : (wp >> 6);
-                const int w = wpos[q] + lane;
-                if (w < W)
-                    xr[q] = rowm[(size_t)jp * W + w] &
-                            (staged ? sh.alive[w] : alive_k[(size_t)w * ALIVE_PAD]);
+                const int wp = uniform(wit[c * 64 + pl[q]]);
+                pos[q] = wp < 0 ? 0 : (wp >> 6);
             }
         }
-        for (int q = 0; q < mine; ++q) {
-            const int p = pl[q];
-            const int jp = c * 64 + p;
-            const u64 *row = rowm + (size_t)jp * W;
-            int found = -1;
-            u64 x = xr[q];
-            for (int pos = wpos[q];;) {
-                const u64 b = ballot(x != 0);
-                if (b) {
-                    // new witness: among the alive dominators in the first word that
-                    // has any, the one with the most dominators of its own (a proxy
-                    // for the deepest, which stays alive longest)
-                    const int L = __ffsll((long long)b) - 1;
-                    const unsigned lo = __builtin_amdgcn_readlane((unsigned)x, L);
-                    const unsigned hi = __builtin_amdgcn_readlane((unsigned)(x >> 32), L);
-                    const u64 xl = ((u64)hi << 32) | lo;
-                    const int cand = (pos + L) * 64 + lane;
-                    const bool has = (xl >> lane) & 1ull;
-                    const u64 key = has ? (((u64)(unsigned)I.P.nd[cand] << 32) | (unsigned)(~cand)) : 0ull;
-                    const u64 best = wave_max_u64(key);
-                    found = (int)~(unsigned)(best & 0xffffffffull);
-                    break;
+        for (;;) {
+            u64 x0[PER], x1[PER];
+#pragma unroll
+            for (int q = 0; q < PER; ++q) {
+                x0[q] = 0;
+                x1[q] = 0;
+                if (state[q] == 0) {
+                    const u64 *__restrict__ row = rowm + (size_t)(c * 64 + pl[q]) * W;
+                    const int w = pos[q] + 2 * lane;
+                    if (w < W)
+                        x0[q] = row[w] & (staged ? sh.alive[w] : alive_k[(size_t)w * ALIVE_PAD]);
+                    if (w + 1 < W)
+                        x1[q] = row[w + 1] &
+                                (staged ? sh.alive[w + 1] : alive_k[(size_t)(w + 1) * ALIVE_PAD]);
                 }
-                pos += 64;
-                if (pos >= W) break;
-                const int w = pos + lane;
-                x = 0;
-                if (w < W) x = row[w] & (staged ? sh.alive[w] : alive_k[(size_t)w * ALIVE_PAD]);
             }
+            int searching = 0;
+#pragma unroll
+            for (int q = 0; q < PER; ++q) {
+                if (state[q] != 0) continue;
+                const u64 b = ballot((x0[q] | x1[q]) != 0);
+                if (b) {
+                    const int L = __ffsll((long long)b) - 1;
+                    const u64 a0 = read_lane64(x0[q], L);
+                    const u64 a1 = read_lane64(x1[q], L);
+                    fw[q] = a0 ? a0 : a1;
+                    fwi[q] = pos[q] + 2 * L + (a0 ? 0 : 1);
+                    state[q] = 1;
+                } else {
+                    pos[q] += 128;
+                    if (pos[q] >= W) state[q] = 2;
+                    else searching = 1;
+                }
+            }
+            if (!searching) break;
+        }
+        // new witness: among the alive dominators in the first word that has
+        // any, the one with the most dominators of its own (a proxy for the
+        // deepest, which stays alive longest); the loads of all points overlap
+        u64 key[PER];
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            key[q] = 0;
+            const int cand = fwi[q] * 64 + lane;
+            if (state[q] == 1 && ((fw[q] >> lane) & 1ull))
+                key[q] = ((u64)(unsigned)I.P.nd[cand] << 32) | (unsigned)(~cand);
+        }
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            if (state[q] != 1 && state[q] != 2) continue;
+            int found = -1;
+            if (state[q] == 1) found = (int)~(unsigned)(wave_max_u64(key[q]) & 0xffffffffull);
+            const int jp = c * 64 + pl[q];
             if (lane == 0) wit[jp] = found;
-            if (found < 0 && lane == 0) atomicOr(&sh.newly, 1ull << p);
+            if (found < 0 && lane == 0) atomicOr(&sh.newly, 1ull << pl[q]);
         }
         __syncthreads();
         newly = aw & uniform(sh.newly);

@@ -314,6 +314,15 @@ struct HostPlan {
     int max_W;
 };
 
+// Copies `bytes` host bytes to device memory `dst` with kernels whose
+// arguments carry the data (graph-capturable; the host buffer may be reused
+// as soon as the call returns). `bytes` is a multiple of 4.
+hipError_t upload(const void *src, size_t bytes, void *dst, hipStream_t s);
+
+// Generation step of served populations (descriptor table in ws).
+size_t evolve_header_bytes(int B);
+hipError_t launch_evolve(const nsga3_evolve_slot *slots, int B, char *ws, hipStream_t s);
+
 hipError_t launch_prepare(const HostPlan &hp, const BatchView &bv, hipStream_t s);
 hipError_t launch_nd_sort(const HostPlan &hp, const BatchView &bv, hipStream_t s);
 hipError_t launch_normalize(const HostPlan &hp, const BatchView &bv, hipStream_t s);
@@ -322,7 +331,6 @@ hipError_t launch_niche(const HostPlan &hp, const BatchView &bv, hipStream_t s);
 
 // dominance work items of an instance (waves): block row jb holds
 // floor(jb / G) + 1 items of up to G column tiles each
-constexpr int DOM_G_DEFAULT = 8;
 long long dominance_items(int W, int G);
 
 }  // namespace nsga3

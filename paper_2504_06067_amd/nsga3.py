@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(_HERE, "libnsga3.so")
 
 OK, EINVAL, EWORKSPACE, EHIP, ENONFINITE, EINTERNAL = 0, -1, -2, -3, -4, -5
 UNRANKED = 0x7FFFFFFF
+MAX_BATCH = 1024
 _NAMES = {0: "OK", -1: "EINVAL", -2: "EWORKSPACE", -3: "EHIP", -4: "ENONFINITE", -5: "EINTERNAL"}
 
 _lib = None
@@ -48,12 +49,17 @@ def lib():
     L.nsga3_batched_workspace_bytes.restype = sz
     L.nsga3_select_batched.argtypes = [P, i32, P, sz, P]
     L.nsga3_read_status_batched.argtypes = [P, i32, P, P, P]
+    L.nsga3_instance_workspace_bytes.argtypes = [i32, i32, i32, i32]
+    L.nsga3_instance_workspace_bytes.restype = sz
+    L.nsga3_evolve_workspace_bytes.argtypes = [i32]
+    L.nsga3_evolve_workspace_bytes.restype = sz
+    L.nsga3_evolve_batched.argtypes = [P, i32, P, sz, P]
     L.nsga3_version.restype = ctypes.c_char_p
     L.nsga3_profile_enable.argtypes = [ctypes.c_char_p]
     L.nsga3_profile_read.argtypes = [ctypes.c_char_p, P, P, P]
     for f in ("nsga3_nd_sort", "nsga3_normalize", "nsga3_associate", "nsga3_niche",
               "nsga3_select", "nsga3_read_status", "nsga3_profile_enable", "nsga3_profile_read",
-              "nsga3_select_batched", "nsga3_read_status_batched"):
+              "nsga3_select_batched", "nsga3_read_status_batched", "nsga3_evolve_batched"):
         getattr(L, f).restype = i32
     _lib = L
     return L
@@ -70,6 +76,18 @@ def _stream(device):
 def _check(rc, what):
     if rc != OK:
         raise Nsga3Error(rc, what)
+
+
+def status_from_bits(bits):
+    """Public status code of a raw status word read from a workspace region
+    (non-finite input first, then an invalid reference row, then internal)."""
+    if bits & 1:
+        return ENONFINITE
+    if bits & 2:
+        return EINVAL
+    if bits & 4:
+        return EINTERNAL
+    return OK
 
 
 def workspace_bytes(M, m, H, N):
@@ -204,14 +222,16 @@ class Instance(ctypes.Structure):
     _fields_ = [("F", ctypes.c_void_p), ("Z", ctypes.c_void_p), ("selected", ctypes.c_void_p),
                 ("rank", ctypes.c_void_p), ("pi", ctypes.c_void_p), ("dist", ctypes.c_void_p),
                 ("M", ctypes.c_int32), ("m", ctypes.c_int32), ("H", ctypes.c_int32),
-                ("N", ctypes.c_int32), ("seed", ctypes.c_uint64), ("tile", ctypes.c_int32 * 4)]
+                ("N", ctypes.c_int32), ("seed", ctypes.c_uint64), ("tile", ctypes.c_int32 * 4),
+                ("ws", ctypes.c_void_p), ("ws_bytes", ctypes.c_size_t)]
 
 
 class Batch:
     """A batch of independent selections run by one nsga3_select_batched call.
 
     problems: sequence of dicts with F [M][m] and Z [H][m] (float32 CUDA), N,
-    seed and optionally tile (up to 4 ints, 0 = automatic). Outputs are
+    seed and optionally tile (up to 4 ints, 0 = the library's choice; when
+    absent, the autotuned table's entry for the instance's shape). Outputs are
     allocated once here: ``selected[b]`` and, with intermediates=True,
     ``rank[b]``, ``pi[b]``, ``dist[b]``. ``run()`` enqueues the call on the
     current stream; it may be repeated (and captured in a graph)."""
@@ -253,7 +273,11 @@ class Batch:
             e.dist = d.data_ptr() if d is not None else None
             e.M, e.m, e.H, e.N = M, m, H, N
             e.seed = int(q["seed"]) & (2**64 - 1)
-            t = list(q.get("tile") or [])
+            t = q.get("tile")
+            if t is None:
+                from . import autotune
+                t = autotune.lookup(M, m, H)
+            t = list(t)
             for i in range(4):
                 e.tile[i] = int(t[i]) if i < len(t) else 0
         self.device = dev
@@ -275,6 +299,50 @@ class Batch:
                                                _stream(self.device), st),
                "nsga3_read_status_batched")
         return list(st)
+
+
+EVOLVE_GENERATION, EVOLVE_POPULATION, EVOLVE_INIT = 0, 1, 2
+
+
+class EvolveSlot(ctypes.Structure):
+    """``nsga3_evolve_slot`` of the C header."""
+    _fields_ = [("X_old", ctypes.c_void_p), ("sel", ctypes.c_void_p), ("F_old", ctypes.c_void_p),
+                ("X_new", ctypes.c_void_p), ("F_new", ctypes.c_void_p), ("A", ctypes.c_void_p),
+                ("N", ctypes.c_int32), ("d", ctypes.c_int32), ("m", ctypes.c_int32),
+                ("generation", ctypes.c_int32), ("seed", ctypes.c_uint64), ("mode", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+def instance_workspace_bytes(M, m, H, N):
+    return int(lib().nsga3_instance_workspace_bytes(int(M), int(m), int(H), int(N)))
+
+
+def evolve_workspace_bytes(B):
+    return int(lib().nsga3_evolve_workspace_bytes(int(B)))
+
+
+def evolve_batched(slots, ws_buf, stream=None, device=None):
+    """Enqueue one generation step for a ctypes array of EvolveSlot."""
+    st = stream if stream is not None else _stream(device or ws_buf.device)
+    _check(lib().nsga3_evolve_batched(slots, len(slots), _ptr(ws_buf), ws_buf.numel(), st),
+           "nsga3_evolve_batched")
+
+
+def evolve(mode, N, d, m, A, seed, generation, X_new, F_new, X_old=None, F_old=None, sel=None,
+           ws=None):
+    """One generation step of a single population (tensors on the GPU)."""
+    slots = (EvolveSlot * 1)()
+    e = slots[0]
+    e.X_old, e.F_old, e.sel = (X_old.data_ptr() if X_old is not None else None,
+                               F_old.data_ptr() if F_old is not None else None,
+                               sel.data_ptr() if sel is not None else None)
+    e.X_new, e.F_new, e.A = X_new.data_ptr(), F_new.data_ptr(), A.data_ptr()
+    e.N, e.d, e.m, e.generation = int(N), int(d), int(m), int(generation)
+    e.seed = int(seed) & (2**64 - 1)
+    e.mode = int(mode)
+    ws = ws or Workspace(X_new.device)
+    buf = ws.get(evolve_workspace_bytes(1))
+    evolve_batched(slots, buf, device=X_new.device)
 
 
 def batched_workspace_bytes(problems):

@@ -126,3 +126,34 @@ def random_small(rng, M, m, kind="continuous"):
     if kind == "equal":
         return np.ones((M, m), np.float32)
     raise ValueError(kind)
+
+
+# Served requests: m -> reference set (single layer p, or two layers (p1, p2)).
+SERVED_REFS = {3: (40,), 5: (8,), 10: (3,), 15: (2, 1)}
+SERVED_D = 12
+SERVED_GENERATIONS = 50
+
+
+def served_refs(m):
+    p = SERVED_REFS[m]
+    return das_dennis(m, p[0]) if len(p) == 1 else das_dennis_two_layer(m, p[0], p[1])
+
+
+def served_trace(seed=0, count=256, qps=1.0, lo=1000, hi=100000, ms=(3, 5, 10, 15),
+                 d=SERVED_D, generations=SERVED_GENERATIONS):
+    """Request stream: Poisson arrivals at rate `qps` (seconds), 2N
+    log-uniform in [lo, hi] (even), m uniform over `ms`; each request carries
+    its reference set, a seeded N(0, 1) objective-map matrix A [m][d-1] and
+    its own seed. Arrival times are returned relative to the first (0)."""
+    rng = np.random.default_rng(seed)
+    gaps = rng.exponential(1.0 / qps, count)
+    t = np.concatenate([[0.0], np.cumsum(gaps[1:])])
+    out = []
+    for r in range(count):
+        M = 2 * int(round(math.exp(rng.uniform(math.log(lo), math.log(hi))) / 2))
+        m = int(ms[rng.integers(len(ms))])
+        ra = np.random.default_rng(seed * 100003 + r)
+        A = ra.standard_normal((m, d - 1)).astype(np.float32)
+        out.append(dict(rid=r, arrival=float(t[r]), M=M, N=M // 2, m=m, d=d, Z=served_refs(m),
+                        A=A, generations=generations, seed=seed * 1000003 + r))
+    return out

@@ -77,7 +77,8 @@ class _Inst(ctypes.Structure):
     _fields_ = [("F", ctypes.c_void_p), ("Z", ctypes.c_void_p), ("selected", ctypes.c_void_p),
                 ("rank", ctypes.c_void_p), ("pi", ctypes.c_void_p), ("dist", ctypes.c_void_p),
                 ("M", ctypes.c_int32), ("m", ctypes.c_int32), ("H", ctypes.c_int32),
-                ("N", ctypes.c_int32), ("seed", ctypes.c_uint64), ("tile", ctypes.c_int32 * 4)]
+                ("N", ctypes.c_int32), ("seed", ctypes.c_uint64), ("tile", ctypes.c_int32 * 4),
+                ("ws", ctypes.c_void_p), ("ws_bytes", ctypes.c_size_t)]
 
 
 def _batch(shapes, tiles=None):
@@ -90,8 +91,8 @@ def _batch(shapes, tiles=None):
 
 
 def test_instance_struct_matches_header():
-    # six pointers, four int32, a uint64 and int32[4]
-    assert ctypes.sizeof(_Inst) == 88
+    # six pointers, four int32, a uint64, int32[4], a pointer and a size
+    assert ctypes.sizeof(_Inst) == 104
     src = open(os.path.join(ROOT, "include", "nsga3.h")).read()
     body = src[src.index("typedef struct nsga3_instance"):src.index("} nsga3_instance;")]
     fields = [ln.split(";")[0].split()[-1].lstrip("*") for ln in body.splitlines()[1:] if ";" in ln]
