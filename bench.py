@@ -43,6 +43,9 @@ def parse():
     ap.add_argument("--only-batched", action="store_true",
                     help="run the batched comparison alone (for profiling it separately)")
     ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--calib-copy-mb", type=int, default=0,
+                    help="run one device-to-device copy of this size first (the reference "
+                         "kernel that scales HBM counters in a --pmc run)")
     ap.add_argument("--only-served", action="store_true",
                     help="run the served comparison alone (for profiling it separately)")
     ap.add_argument("--served-requests", type=int, default=64)
@@ -245,6 +248,13 @@ def main():
     out = torch.empty(N, dtype=torch.int32, device=dev)
     stream = torch.cuda.current_stream(dev)
 
+    if args.calib_copy_mb:
+        n = args.calib_copy_mb << 20
+        src = torch.ones(n, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize(dev)
+        del src, dst
     for _ in range(args.warmup):
         nsga3.select(F, Z, N, inst["seed"], ws=ws, out=out)
     torch.cuda.synchronize(dev)
@@ -269,6 +279,9 @@ def main():
         raise RuntimeError("device status not OK after the timed region")
 
     step_ms = np.array([a.elapsed_time(b) for a, b in zip(starts, stops)])
+    from paper_2504_06067_amd import profiling
+    rec = profiling.read_traffic(os.path.join(ROOT, "profiles", f"k_dominance_{args.workload}_traffic.json"))
+    traffic = rec["traffic_bytes"] if rec else None
     dom_avg_s = dom_ms / max(dom_n, 1) / 1e3
     compares = M * (M - 1) * m  # 2m compares per unordered pair
     achieved = compares / dom_avg_s if dom_avg_s > 0 else 0.0
@@ -302,7 +315,10 @@ def main():
             "peak": VALU_PEAK_OPS / 1e12,
             "unit": "TOP/s (fp32 compare lane-ops)",
             "frac": achieved / VALU_PEAK_OPS,
-            "traffic": None,
+            "traffic": traffic,
+            "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled by "
+                            "a plain copy of known size)",
+            "algorithmic_bytes": M * M // 8 + M * m * 4,
             "avg_kernel_ms": dom_avg_s * 1e3,
             "launches_timed": dom_n,
         },

@@ -69,8 +69,7 @@ enum {
 
 /* Workspace size in bytes for one selection of M merged points, m objectives,
  * H references, N survivors. Pure host function. The dominant term is the
- * bit-packed dominance matrix, ceil(M/64)^2 * 512 bytes, held twice (as
- * computed, and a row-major copy for the front peeling). Returns 0 for
+ * bit-packed dominance matrix, ceil(M/64)^2 * 512 bytes. Returns 0 for
  * arguments that every compute call would reject. */
 size_t nsga3_workspace_bytes(int32_t M, int32_t m, int32_t H, int32_t N);
 

@@ -31,13 +31,12 @@ Layout make_layout(int M, int m, int H, int N) {
     L.ft = take((size_t)m * Mp * 4);
     L.nd = take(Mp * 4);
     L.mask = take(W * Mp * 8);
-    L.rowm = take(W * Mp * 8);
-    L.wit = take(Mp * 4);
-    // alive ring: ns slots of W words, one 128-byte line per word
-    L.ns = (int)((64ull << 20) / (W * 128));
+    // alive ring: ns slots of W packed words (one slot per front)
+    const size_t slot_bytes = (size_t)alive_slot_words(L.W) * 8;
+    L.ns = (int)((16ull << 20) / slot_bytes);
     if (L.ns > 254) L.ns = 254;
     if (L.ns < 8) L.ns = 8;
-    L.alive = take((size_t)L.ns * W * 128);
+    L.alive = take((size_t)L.ns * slot_bytes);
     L.facc = take(3 * PEEL_SLOT * 8);  // front-peeling counter ring
     L.list = take(Mp * 4);
     L.fn = take(Mp * (size_t)m * 4);
@@ -54,7 +53,6 @@ Layout make_layout(int M, int m, int H, int N) {
     L.members = take(Mp * 4);
     L.picked = take(Mp * 4);
     L.remain = take((W + (size_t)H + 2) * 8);
-    L.tiles = take(((size_t)(M + 4095) / 4096 + 1) * 4);
     L.total = o;
     return L;
 }
@@ -66,8 +64,6 @@ Ptrs carve(const Layout &L, void *ws) {
     P.ft = (float *)(b + L.ft);
     P.nd = (int *)(b + L.nd);
     P.mask = (u64 *)(b + L.mask);
-    P.rowm = (u64 *)(b + L.rowm);
-    P.wit = (int *)(b + L.wit);
     P.alive = (u64 *)(b + L.alive);
     P.facc = (u64 *)(b + L.facc);
     P.list = (int *)(b + L.list);
@@ -85,7 +81,6 @@ Ptrs carve(const Layout &L, void *ws) {
     P.members = (int *)(b + L.members);
     P.picked = (int *)(b + L.picked);
     P.remain = (u64 *)(b + L.remain);
-    P.tiles = (int *)(b + L.tiles);
     return P;
 }
 
@@ -116,7 +111,7 @@ static int to_status(hipError_t e) { return e == hipSuccess ? NSGA3_OK : NSGA3_E
 
 // Byte offsets inside the batch header.
 struct HeaderLayout {
-    size_t tab, pt_pref, ref_pref, chunk_pref, tile_pref, order, dom_pref, asc_pref, ticket, total;
+    size_t tab, pt_pref, ref_pref, chunk_pref, order, dom_pref, asc_pref, ticket, total;
 };
 
 static HeaderLayout header_layout(int B) {
@@ -127,11 +122,10 @@ static HeaderLayout header_layout(int B) {
     h.pt_pref = take((size_t)(B + 1) * 4);
     h.ref_pref = take((size_t)(B + 1) * 4);
     h.chunk_pref = take((size_t)(B + 1) * 4);
-    h.tile_pref = take((size_t)(B + 1) * 4);
     h.order = take((size_t)B * 4);
     h.dom_pref = take((size_t)(B + 1) * 8);
     h.asc_pref = take((size_t)(B + 1) * 8);
-    h.ticket = take(8);
+    h.ticket = take((size_t)TICKET_SHARDS * TICKET_STRIDE * 8);
     h.total = o;
     return h;
 }
@@ -216,9 +210,9 @@ static void plan(std::vector<Spec> &spec, char *ws, int run, Plan &p) {
     for (int b = 0; b < B; ++b) p.base[b] = spec[b].own ? spec[b].own : ws + p.region[b];
 
     std::vector<Inst> tab(B);
-    std::vector<int> pt(B + 1), ref(B + 1), chunk(B + 1), tile(B + 1), order(B);
+    std::vector<int> pt(B + 1), ref(B + 1), chunk(B + 1), order(B);
     std::vector<long long> dom(B + 1), asc(B + 1);
-    pt[0] = ref[0] = chunk[0] = tile[0] = 0;
+    pt[0] = ref[0] = chunk[0] = 0;
     for (int b = 0; b < B; ++b) {
         const Layout &L = p.lay[b];
         Inst I = spec[b].I;
@@ -230,12 +224,10 @@ static void plan(std::vector<Spec> &spec, char *ws, int run, Plan &p) {
         I.G = spec[b].tile[0] > 0 ? spec[b].tile[0] : dominance_group(L.W);
         I.R = spec[b].tile[1] > 0 ? spec[b].tile[1] : auto_slice(I.H, sum_W);
         I.nslice = (I.H + I.R - 1) / I.R;
-        I.ntiles = (I.M + COMPACT_TILE - 1) / COMPACT_TILE;
         tab[b] = I;
         pt[b + 1] = pt[b] + (int)((I.M + PT_ALIGN - 1) / PT_ALIGN * PT_ALIGN);
         ref[b + 1] = ref[b] + (int)((I.Hp + PT_ALIGN - 1) / PT_ALIGN * PT_ALIGN);
         chunk[b + 1] = chunk[b] + I.W;
-        tile[b + 1] = tile[b] + I.ntiles;
         order[b] = b;
     }
     std::stable_sort(order.begin(), order.end(),
@@ -245,7 +237,6 @@ static void plan(std::vector<Spec> &spec, char *ws, int run, Plan &p) {
     hp.npt = pt[B];
     hp.nref = ref[B];
     hp.nchunk = chunk[B];
-    hp.ntile = tile[B];
     hp.ngroups = 0;
     hp.max_W = 0;
     dom[0] = asc[0] = 0;
@@ -268,13 +259,13 @@ static void plan(std::vector<Spec> &spec, char *ws, int run, Plan &p) {
 
     // header bytes
     const HeaderLayout &hl = p.hl;
-    p.hdr.assign(hl.total, 0);
+    // everything before the ticket counters (which k_init zeroes) is uploaded
+    p.hdr.assign(hl.ticket, 0);
     unsigned char *h = p.hdr.data();
     memcpy(h + hl.tab, tab.data(), (size_t)B * sizeof(Inst));
     memcpy(h + hl.pt_pref, pt.data(), (size_t)(B + 1) * 4);
     memcpy(h + hl.ref_pref, ref.data(), (size_t)(B + 1) * 4);
     memcpy(h + hl.chunk_pref, chunk.data(), (size_t)(B + 1) * 4);
-    memcpy(h + hl.tile_pref, tile.data(), (size_t)(B + 1) * 4);
     memcpy(h + hl.order, order.data(), (size_t)B * 4);
     memcpy(h + hl.dom_pref, dom.data(), (size_t)(B + 1) * 8);
     memcpy(h + hl.asc_pref, asc.data(), (size_t)(B + 1) * 8);
@@ -285,7 +276,6 @@ static void plan(std::vector<Spec> &spec, char *ws, int run, Plan &p) {
     bv.pt_pref = (const NSGA3_RO int *)(hd + hl.pt_pref);
     bv.ref_pref = (const NSGA3_RO int *)(hd + hl.ref_pref);
     bv.chunk_pref = (const NSGA3_RO int *)(hd + hl.chunk_pref);
-    bv.tile_pref = (const NSGA3_RO int *)(hd + hl.tile_pref);
     bv.order = (const NSGA3_RO int *)(hd + hl.order);
     bv.dom_pref = (const NSGA3_RO long long *)(hd + hl.dom_pref);
     bv.asc_pref = (const NSGA3_RO long long *)(hd + hl.asc_pref);

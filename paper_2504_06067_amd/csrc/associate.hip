@@ -79,13 +79,22 @@ __global__ __launch_bounds__(256) void k_associate(BatchView bv, int gs, int gn,
     const int i = pb * 64 + lane_id();
     const bool in = i < n;
     const int x = in ? I.P.list[i] : I.P.list[pb * 64];
-    const float *__restrict__ Fn = I.Fn;
+    // in a whole selection Fn is formed here from F, the ideal point and the
+    // intercepts (the same float32 operations as the normalization's output)
+    const bool fused = (bv.run & RUN_NORM) != 0;
+    const float *__restrict__ Fn = fused ? I.F : I.Fn;
     // unit directions: written by k_prep, read-only here (invariant loads)
     const NSGA3_RO float *wn = (const NSGA3_RO float *)I.P.wn;
     const int H = I.H, Hp = I.Hp;
+    // ideal point and reciprocal intercepts: written by the normalization,
+    // read-only here (invariant loads)
+    const NSGA3_RO Ctrl *cc = (const NSGA3_RO Ctrl *)I.P.ctrl;
     float f[MO];
 #pragma unroll
-    for (int k = 0; k < MO; ++k) f[k] = Fn[(size_t)x * MO + k];
+    for (int k = 0; k < MO; ++k) {
+        f[k] = Fn[(size_t)x * MO + k];
+        if (fused) f[k] = (f[k] - cc->zf[k]) * cc->recip[k];
+    }
     const int h0 = sl * I.R;
     const int h1 = min(h0 + I.R, H);
     float best = INFINITY;

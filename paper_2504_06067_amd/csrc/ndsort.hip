@@ -40,7 +40,7 @@ __global__ __launch_bounds__(256) void k_init(BatchView bv) {
             I.front_info[3] = 0;
         }
     }
-    if (blockIdx.x == 0 && t == 0) *bv.ticket = 0;
+    if (blockIdx.x == 0 && t < TICKET_SHARDS) bv.ticket[t * TICKET_STRIDE] = 0;
     if (t < NSGA3_MAX_OBJECTIVES) {
         ctrl->zmin_enc[t] = 0xffffffffu;
         ctrl->fmax_enc[t] = 0u;
@@ -71,7 +71,7 @@ __global__ __launch_bounds__(256) void k_prep(BatchView bv, int npt) {
             if (j < M) I.rank[j] = NSGA3_UNRANKED;
             if ((j & 63) == 0) {
                 const int valid = M - j;
-                I.P.alive[(size_t)(j >> 6) * ALIVE_PAD] =
+                I.P.alive[(size_t)(j >> 6)] =
                     valid >= 64 ? ~0ull : (valid <= 0 ? 0ull : ((1ull << valid) - 1));
             }
         }
@@ -257,22 +257,18 @@ __global__ __launch_bounds__(256) void k_dominance(BatchView bv, int gs, int gn,
 
 // Front peeling.
 //
-// Chunk c of an instance holds its 64 points 64c .. 64c+63. Front 0 is
-// {j : no dominator} (fused counts of the dominance kernel). A point j alive
-// at front k > 0 belongs to it iff no alive point dominates it. Fronts after
-// the first are found with witnesses: every alive point keeps one alive
-// dominator (its witness) and is re-examined only once its witness has been
-// ranked. The re-examination resumes the scan of j's row at the witness's
-// word: the words before it held no alive dominator when they were scanned,
-// and the alive set only shrinks. Over the whole peel each row is read about
-// once. The scans read a row-major copy of the dominance matrix (row j = the W
-// words of point j's dominators), which each workgroup writes for its own
-// chunks when their instance starts front 1; an instance whose front 0
-// already fills N never builds it. The peel of an instance stops once its
-// ranked fronts hold n_stop points.
+// Chunk c of an instance holds its 64 points 64c .. 64c+63. Every point keeps
+// the number of its dominators that are still alive (not yet ranked), starting
+// from the fused counts of the dominance kernel; front k is the set of alive
+// points whose count is zero. When front k - 1 is known, each chunk subtracts,
+// for every block w of 64 points that lost members to front k - 1, the
+// popcount of (its points' word w of the dominance matrix) AND (those
+// members): one coalesced 512-byte load per block w and wave, all blocks in
+// flight at once, no per-point searching. The peel of an instance stops once
+// its ranked fronts hold n_stop points.
 //
 // Scheduling. While ranking front 0, workgroups claim chunks (of any
-// instance) from a ticket counter until every chunk is claimed; a workgroup
+// instance) from sharded ticket counters until every chunk is claimed; a workgroup
 // then owns its chunks for all later fronts and processes them front by
 // front. Only running workgroups claim, and no workgroup waits before all
 // chunks are claimed and ranked for front 0; later waits are for lower fronts
@@ -281,79 +277,63 @@ __global__ __launch_bounds__(256) void k_dominance(BatchView bv, int gs, int gn,
 // the front-0 wait would time out into an error status.
 //
 // Completion. Per front, chunk c adds (points ranked << 32) + 1 to shard
-// counter c % PEEL_SHARDS of its instance (a fire-and-forget atomic); a
-// waiting workgroup reads the 32 shards with one wave and sums them. Counters
-// live in a ring of three front slots per instance; the slot of front k + 1
-// is cleared while front k is processed (after front k - 1 completed, nobody
-// reads it).
+// counter c % PEEL_SHARDS of its instance; the chunk whose add completes its
+// shard adds the shard's (points << 32) + 1 to the front total, which a
+// waiting workgroup polls with one load (the shards spread the atomics over
+// many addresses, the total keeps the polling to one word). Counters live in
+// a ring of three front slots per instance; each chunk clears its shard of
+// front k + 1's slot (chunk 0 also its total) when it publishes front k:
+// that slot last held front k - 2, whose waits all ended before front k - 1
+// could complete.
 //
 // Memory ordering. Alive words and counters are written with agent-scope
 // atomic stores, which go to the coherent level; each chunk waits for its
 // stores before its counter add. Waiters poll the counters with relaxed
-// atomic loads. Alive words are then read with ordinary cached loads: the
-// word of each chunk sits alone on a 128-byte line of a per-front slot, so
-// no line is written by two workgroups and none is cached before it is read;
-// slots are reused only after `ns` fronts, and then an agent-scope acquire
-// drops stale copies. The row-major copy and the witnesses of a chunk are
-// touched only by its owner.
+// atomic loads. Alive words are then read with ordinary cached loads. The
+// words of one front are packed in their own slot of a ring: a slot is
+// written only while the front before it is processed and read only after
+// that front completed, so no workgroup holds a line of it while it is being
+// written; slots are reused only after `ns` fronts, and then an agent-scope
+// acquire drops stale copies. A chunk's counts are read and written only by
+// wave 0 of its owner, whose publish waits for its stores.
 //
 // Control flow is wave-uniform around every workgroup barrier: wave 0 makes
 // the scheduling decisions with all its lanes and shares them through LDS.
+// Barriers order LDS only (they do not wait for global stores in flight).
 constexpr int PEEL_WAVES = 8;
 constexpr int PEEL_OWN_CAP = 1024;
-constexpr int PEEL_LDS_ALIVE = 2048;  // alive words staged in LDS (M <= 131072)
+constexpr int PEEL_LDS_ALIVE = 2048;  // words staged in LDS (M <= 131072)
+constexpr int PEEL_BATCH = 16;        // matrix loads in flight per wave
 
 __device__ __forceinline__ u64 *peel_slot(u64 *ring, int k) { return ring + (size_t)(k % 3) * PEEL_SLOT; }
 
-// Alive bitset of front k: slot k % ns of the alive ring.
+// Alive bitset of front k: slot k % ns of the alive ring (W words, padded to
+// whole 128-byte lines).
 __device__ __forceinline__ u64 *alive_slot(u64 *aring, int W, int ns, int k) {
-    return aring + (size_t)(k % ns) * W * ALIVE_PAD;
+    return aring + (size_t)(k % ns) * alive_slot_words(W);
 }
 
 struct PeelShared {
     int own_b[PEEL_OWN_CAP];    // instance of each owned chunk
     int own_c[PEEL_OWN_CAP];    // chunk within its instance
     int own_cum[PEEL_OWN_CAP];  // points in the instance's fronts seen so far (-1: done)
-    union {                     // the transpose (front 1 start) and the scans never overlap
-        u64 alive[PEEL_LDS_ALIVE];
-        u64 tile[64][65];
-    };
+    u64 dead[PEEL_LDS_ALIVE];   // members of front k - 1, per block of 64 points
+    int part[PEEL_WAVES][64];   // per-wave partial decrements of the chunk's counts
     u64 val;
-    u64 need;
-    u64 newly;
     int flag;
 };
 
-// Row-major copy of chunk c's rows: rowm[j][w] = mask[w][j], through a
-// padded 64 x 64-word LDS tile (coalesced reads and writes).
-__device__ void peel_transpose(CInst &I, int c, PeelShared &sh) {
-    const int lane = lane_id();
-    const int wv = uniform((int)(threadIdx.x >> 6));
-    const int W = I.W, Mp = I.Mp;
-    const u64 *__restrict__ mask = I.P.mask;
-    u64 *__restrict__ rowm = I.P.rowm;
-    for (int w0 = 0; w0 < W; w0 += 64) {
-#pragma unroll
-        for (int q = 0; q < 64 / PEEL_WAVES; ++q) {
-            const int wl = wv * (64 / PEEL_WAVES) + q;
-            const int w = w0 + wl;
-            sh.tile[wl][lane] = (w < W) ? mask[(size_t)w * Mp + (size_t)c * 64 + lane] : 0ull;
-        }
-        __syncthreads();
-#pragma unroll
-        for (int q = 0; q < 64 / PEEL_WAVES; ++q) {
-            const int r = wv * (64 / PEEL_WAVES) + q;
-            const int w = w0 + lane;
-            if (w < W) rowm[((size_t)c * 64 + r) * W + w] = sh.tile[lane][r];
-        }
-        __syncthreads();
-    }
-    if (wv == 0) I.P.wit[c * 64 + lane] = -1;
+// Members of front k - 1 in block w (staged in LDS when STAGED).
+template <bool STAGED>
+__device__ __forceinline__ u64 dead_word(const PeelShared &sh, const u64 *alive_p,
+                                         const u64 *alive_k, int w) {
+    if (STAGED) return sh.dead[w];
+    return alive_p[w] & ~alive_k[w];
 }
 
 // Ranks the points of chunk c that are alive at front k and have no alive
 // dominator; publishes the chunk's result. All waves take part.
-// STAGED: the alive words of front k are copied to LDS (W <= PEEL_LDS_ALIVE);
+// STAGED: the members of front k - 1 are staged in LDS (W <= PEEL_LDS_ALIVE);
 // a compile-time choice, so that no pointer ever selects between LDS and
 // global memory.
 template <bool STAGED>
@@ -363,135 +343,74 @@ __device__ void peel_chunk_impl(CInst &I, int k, int c, PeelShared &sh) {
     const int W = I.W, ns = I.ns;
     const u64 *alive_k = alive_slot(I.P.alive, W, ns, k);
     u64 *alive_n = alive_slot(I.P.alive, W, ns, k + 1);
-    const u64 aw = uniform(alive_k[(size_t)c * ALIVE_PAD]);
+    const u64 aw = uniform(alive_k[c]);
     const int j = c * 64 + lane;
+    int *nd = I.P.nd;
     u64 newly;
     if (k == 0) {
-        newly = aw & ballot(I.P.nd[j] == 0);
+        newly = aw & ballot(nd[j] == 0);
     } else {
-        constexpr bool staged = STAGED;
-        const u64 *__restrict__ rowm = I.P.rowm;
-        int *wit = I.P.wit;
-        __syncthreads();  // the previous chunk is done with the shared words
-        if (staged && aw != 0)
-            for (int w = threadIdx.x; w < W; w += blockDim.x) sh.alive[w] = alive_k[(size_t)w * ALIVE_PAD];
-        if (wv == 0) sh.newly = 0;
-        __syncthreads();
-        // points whose witness is still alive stay dominated
-        if (wv == 0) {
-            bool need = false;
-            if ((aw >> lane) & 1ull) {
-                const int wj = wit[j];
-                if (wj < 0) {
-                    need = true;
-                } else {
-                    const u64 word = staged ? sh.alive[wj >> 6] : alive_k[(size_t)(wj >> 6) * ALIVE_PAD];
-                    need = ((word >> (wj & 63)) & 1ull) == 0;
+        const u64 *alive_p = alive_slot(I.P.alive, W, ns, k - 1);
+        int left = 0;
+        if (wv == 0) left = nd[j];  // alive dominators before front k - 1 is removed
+        lds_barrier();  // the previous chunk is done with the shared words
+        if (STAGED && aw != 0)
+            for (int w = threadIdx.x; w < W; w += blockDim.x) sh.dead[w] = alive_p[w] & ~alive_k[w];
+        lds_barrier();
+        if (aw != 0) {
+            // wave wv takes blocks wv, wv + PEEL_WAVES, ...; PEEL_BATCH loads in flight
+            const u64 *__restrict__ col = I.P.mask + (size_t)c * 64 + lane;
+            const size_t Mp = (size_t)I.Mp;
+            int acc = 0;
+            for (int w0 = wv; w0 < W; w0 += PEEL_WAVES * PEEL_BATCH) {
+                u64 x[PEEL_BATCH], d[PEEL_BATCH];
+#pragma unroll
+                for (int q = 0; q < PEEL_BATCH; ++q) {
+                    const int w = w0 + q * PEEL_WAVES;
+                    d[q] = w < W ? dead_word<STAGED>(sh, alive_p, alive_k, w) : 0ull;
+                    x[q] = d[q] ? col[(size_t)w * Mp] : 0ull;
                 }
+#pragma unroll
+                for (int q = 0; q < PEEL_BATCH; ++q) acc += __popcll(x[q] & d[q]);
             }
-            sh.need = ballot(need);
+            sh.part[wv][lane] = acc;
         }
-        __syncthreads();
-        const u64 need = uniform(sh.need);
-        // wave wv re-examines the needing points wv, wv + PEEL_WAVES, ... (lane
-        // order)
-        constexpr int PER = 64 / PEEL_WAVES;
-        int pl[PER];
-        int mine = 0;
-        {
-            u64 rest = need;
-            for (int skip = 0; skip < wv && rest; ++skip) rest &= rest - 1;
+        lds_barrier();
+        newly = 0;
+        if (wv == 0 && aw != 0) {
 #pragma unroll
-            for (int q = 0; q < PER; ++q) {
-                pl[q] = rest ? __ffsll((long long)rest) - 1 : -1;
-                if (rest) {
-                    ++mine;
-                    for (int skip = 0; skip < PEEL_WAVES && rest; ++skip) rest &= rest - 1;
-                }
-            }
+            for (int v = 0; v < PEEL_WAVES; ++v) left -= sh.part[v][lane];
+            const bool alive = (aw >> lane) & 1ull;
+            if (alive) nd[j] = left;
+            newly = aw & ballot(alive && left == 0);
         }
-        // All needing points of the wave search together: each round loads the
-        // next 128 words (two per lane) of every point still searching, so the
-        // rounds of different points overlap instead of adding up.
-        int pos[PER], state[PER], fwi[PER];  // state: 0 searching, 1 found, 2 none, 3 unused
-        u64 fw[PER];
-#pragma unroll
-        for (int q = 0; q < PER; ++q) {
-            pos[q] = 0;
-            fwi[q] = 0;
-            fw[q] = 0;
-            state[q] = q < mine ? 0 : 3;
-            if (q < mine) {
-                const int wp = uniform(wit[c * 64 + pl[q]]);
-                pos[q] = wp < 0 ? 0 : (wp >> 6);
-            }
-        }
-        for (;;) {
-            u64 x0[PER], x1[PER];
-#pragma unroll
-            for (int q = 0; q < PER; ++q) {
-                x0[q] = 0;
-                x1[q] = 0;
-                if (state[q] == 0) {
-                    const u64 *__restrict__ row = rowm + (size_t)(c * 64 + pl[q]) * W;
-                    const int w = pos[q] + 2 * lane;
-                    if (w < W)
-                        x0[q] = row[w] & (staged ? sh.alive[w] : alive_k[(size_t)w * ALIVE_PAD]);
-                    if (w + 1 < W)
-                        x1[q] = row[w + 1] &
-                                (staged ? sh.alive[w + 1] : alive_k[(size_t)(w + 1) * ALIVE_PAD]);
-                }
-            }
-            int searching = 0;
-#pragma unroll
-            for (int q = 0; q < PER; ++q) {
-                if (state[q] != 0) continue;
-                const u64 b = ballot((x0[q] | x1[q]) != 0);
-                if (b) {
-                    const int L = __ffsll((long long)b) - 1;
-                    const u64 a0 = read_lane64(x0[q], L);
-                    const u64 a1 = read_lane64(x1[q], L);
-                    fw[q] = a0 ? a0 : a1;
-                    fwi[q] = pos[q] + 2 * L + (a0 ? 0 : 1);
-                    state[q] = 1;
-                } else {
-                    pos[q] += 128;
-                    if (pos[q] >= W) state[q] = 2;
-                    else searching = 1;
-                }
-            }
-            if (!searching) break;
-        }
-        // new witness: among the alive dominators in the first word that has
-        // any, the one with the most dominators of its own (a proxy for the
-        // deepest, which stays alive longest); the loads of all points overlap
-        u64 key[PER];
-#pragma unroll
-        for (int q = 0; q < PER; ++q) {
-            key[q] = 0;
-            const int cand = fwi[q] * 64 + lane;
-            if (state[q] == 1 && ((fw[q] >> lane) & 1ull))
-                key[q] = ((u64)(unsigned)I.P.nd[cand] << 32) | (unsigned)(~cand);
-        }
-#pragma unroll
-        for (int q = 0; q < PER; ++q) {
-            if (state[q] != 1 && state[q] != 2) continue;
-            int found = -1;
-            if (state[q] == 1) found = (int)~(unsigned)(wave_max_u64(key[q]) & 0xffffffffull);
-            const int jp = c * 64 + pl[q];
-            if (lane == 0) wit[jp] = found;
-            if (found < 0 && lane == 0) atomicOr(&sh.newly, 1ull << pl[q]);
-        }
-        __syncthreads();
-        newly = aw & uniform(sh.newly);
     }
     if (wv == 0) {
-        store_relaxed(&alive_n[(size_t)c * ALIVE_PAD], aw & ~newly);
+        const int shard = c % PEEL_SHARDS;
+        u64 *next = peel_slot(I.P.facc, k + 1);
+        // clear this chunk's shard (and, for chunk 0, the total) of front
+        // k + 1's counters: that slot last held front k - 2, whose waits all
+        // ended before front k - 1 could complete; the publish below waits
+        // for these stores, and every front k + 1 publish follows all front k
+        // publishes
+        if (lane == 0) store_relaxed(&next[shard * PEEL_STRIDE], 0ull);
+        if (lane == 0 && c == 0) store_relaxed(&next[PEEL_SHARDS * PEEL_STRIDE], 0ull);
+        store_relaxed(&alive_n[c], aw & ~newly);
         __builtin_amdgcn_s_waitcnt(0);
         u64 *slot = peel_slot(I.P.facc, k);
-        const u64 add = ((u64)__popcll(newly) << 32) | 1ull;
-        __hip_atomic_fetch_add(&slot[(c % PEEL_SHARDS) * PEEL_STRIDE], lane == 0 ? add : 0ull,
-                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (lane == 0) {
+            const u64 add = ((u64)__popcll(newly) << 32) | 1ull;
+            const u64 old = __hip_atomic_fetch_add(&slot[shard * PEEL_STRIDE], add, __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT);
+            // the chunk that completes its shard adds the shard's total to the
+            // front total, the one word that waiters poll
+            const unsigned in_shard = (unsigned)((I.W - shard + PEEL_SHARDS - 1) / PEEL_SHARDS);
+            if ((unsigned)(old & 0xffffffffull) + 1u == in_shard) {
+                const u64 tot = old + add;
+                __hip_atomic_fetch_add(&slot[PEEL_SHARDS * PEEL_STRIDE], (tot & ~0xffffffffull) | 1ull,
+                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
         if ((newly >> lane) & 1ull) I.rank[j] = k;  // read only by later kernels
     }
 }
@@ -509,13 +428,42 @@ __global__ __launch_bounds__(64 * PEEL_WAVES) void k_peel(BatchView bv, int nchu
     // drop cached lines of alive slots read by an earlier call on these workspaces
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
 
-    // front 0: claim and rank chunks until all are claimed
+    // front 0: claim and rank chunks until all are claimed. Ticket shard s
+    // hands out chunks s, s + TICKET_SHARDS, ...; a workgroup starts at its
+    // own shard and moves on when one runs dry (the shards spread the claims
+    // over many addresses)
     int nown = 0;
+    const int home = (int)(blockIdx.x % TICKET_SHARDS);
+    bool home_dry = false;
     for (;;) {
-        if (wv == 0) sh.val = uniform(atomicAdd(bv.ticket, one));
-        __syncthreads();
+        if (wv == 0) {
+            u64 t = ~0ull;
+            for (;;) {
+                if (!home_dry) {
+                    const u64 n = uniform(atomicAdd(&bv.ticket[home * TICKET_STRIDE], one));
+                    const u64 g = (u64)home + (u64)TICKET_SHARDS * n;
+                    if (g < (u64)nchunk) { t = g; break; }
+                    home_dry = true;
+                }
+                // look at every shard at once; claim from one that has chunks left
+                // (starting after the home shard), or stop when none has
+                const u64 n_l = lane < TICKET_SHARDS ? load_relaxed(&bv.ticket[lane * TICKET_STRIDE]) : 0ull;
+                const u64 avail = ballot(lane < TICKET_SHARDS &&
+                                         (u64)lane + (u64)TICKET_SHARDS * n_l < (u64)nchunk);
+                if (avail == 0) break;
+                // the 32 shard bits rotated so that the home shard is bit 0
+                const unsigned a32 = (unsigned)avail;
+                const unsigned rot = home == 0 ? a32 : ((a32 >> home) | (a32 << (32 - home)));
+                const int s = (home + __ffs((int)rot) - 1) % TICKET_SHARDS;
+                const u64 n = uniform(atomicAdd(&bv.ticket[s * TICKET_STRIDE], one));
+                const u64 g = (u64)s + (u64)TICKET_SHARDS * n;
+                if (g < (u64)nchunk) { t = g; break; }
+            }
+            sh.val = t;
+        }
+        lds_barrier();
         const u64 t = uniform(sh.val);
-        __syncthreads();
+        lds_barrier();
         if (t >= (u64)nchunk) break;
         const int b = uniform(find_range(bv.chunk_pref, bv.B, (int)t));
         const int c = (int)t - bv.chunk_pref[b];
@@ -528,7 +476,7 @@ __global__ __launch_bounds__(64 * PEEL_WAVES) void k_peel(BatchView bv, int nchu
         ++nown;
         if (nown == PEEL_OWN_CAP) break;
     }
-    __syncthreads();
+    lds_barrier();
     // a workgroup without chunks has nothing left to do; the owners of the
     // chunks report the front fill
     if (nown == 0) return;
@@ -543,27 +491,27 @@ __global__ __launch_bounds__(64 * PEEL_WAVES) void k_peel(BatchView bv, int nchu
             CInst &I = bv.tab[b];
             // wait for front k - 1 of the instance
             if (wv == 0) {
-                const u64 *slot = peel_slot(I.P.facc, k - 1);
+                const u64 *total = peel_slot(I.P.facc, k - 1) + PEEL_SHARDS * PEEL_STRIDE;
+                const unsigned shards = (unsigned)(I.W < PEEL_SHARDS ? I.W : PEEL_SHARDS);
                 u64 v = 0;
                 int ok = 1;
                 for (unsigned polls = 0;; ++polls) {
-                    // lanes 0..31 read one shard each; the wave sums (count, size)
-                    const u64 part = lane < PEEL_SHARDS ? load_relaxed(&slot[lane * PEEL_STRIDE]) : 0ull;
-                    v = uniform(wave_sum(part));
-                    if ((unsigned)(v & 0xffffffffull) >= (unsigned)I.W) break;
+                    // (points ranked << 32) | shards complete
+                    v = uniform(load_relaxed(total));
+                    if ((unsigned)(v & 0xffffffffull) >= shards) break;
                     if (polls == (1u << 26)) { ok = 0; break; }
                     __builtin_amdgcn_s_sleep(2);
                 }
                 sh.val = v;
                 sh.flag = ok;
             }
-            __syncthreads();
+            lds_barrier();
             const u64 v = uniform(sh.val);
             const int ok = uniform(sh.flag);
             // alive slots are reused only after ns fronts: then cached copies of the
             // slot read ns fronts ago must be dropped before it is read again
             if (k + 1 >= I.ns) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-            __syncthreads();
+            lds_barrier();
             const int size = (int)(v >> 32);
             const int cum = cum_prev + size;
             if (!ok || cum >= I.n_stop || size == 0) {
@@ -577,18 +525,11 @@ __global__ __launch_bounds__(64 * PEEL_WAVES) void k_peel(BatchView bv, int nchu
                 }
                 continue;
             }
-            if (wv == 0) {
-                sh.own_cum[q] = cum;
-                // clear the counters of front k + 1 (last read while waiting for
-                // front k - 2); this chunk's own front-k publish, which front k + 1
-                // waits for, is ordered after these stores
-                if (lane <= PEEL_SHARDS) store_relaxed(&peel_slot(I.P.facc, k + 1)[lane * PEEL_STRIDE], 0ull);
-            }
-            if (k == 1) peel_transpose(I, c, sh);
+            if (wv == 0) sh.own_cum[q] = cum;
             peel_chunk(I, k, c, sh);
             active = 1;
         }
-        __syncthreads();
+        lds_barrier();
         if (!active) break;
     }
 }

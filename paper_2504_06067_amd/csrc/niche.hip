@@ -24,14 +24,13 @@
 //   k_niche_scatter  members of front l into per-reference segments
 //   k_niche_pick     one wave per reference: sort its segment ascending,
 //                    make its picks with a remaining-set bitmask
-//   k_compact_count / k_compact_write   ascending output of S and the picks
+//   k_compact        ascending output of S and the picks
 #include "nsga3_internal.h"
 
 namespace nsga3 {
 
 constexpr int PLAN_THREADS = 1024;
 constexpr int PICK_CAP = 2048;          // segment length kept in LDS by one wave
-constexpr int TILE = COMPACT_TILE;      // compaction tile
 
 // Stage call only (a whole selection counts in the association's final pass).
 __global__ __launch_bounds__(256) void k_niche_count(BatchView bv) {
@@ -437,69 +436,63 @@ __global__ __launch_bounds__(256) void k_niche_pick(BatchView bv) {
     }
 }
 
-// Compaction of {x : rank[x] < l or picked[x]} in ascending order; grid: all
-// instances' tiles.
-__global__ __launch_bounds__(256) void k_compact_count(BatchView bv) {
-    __shared__ long long red[4];
-    const int b = uniform(find_range(bv.tile_pref, bv.B, (int)blockIdx.x));
-    CInst &I = bv.tab[b];
-    const int l = I.front_info[0];
-    const int M = I.M;
-    const int tile = (int)blockIdx.x - bv.tile_pref[b];
-    const int base = tile * TILE;
-    long long c = 0;
-    for (int i = threadIdx.x; i < TILE; i += 256) {
-        const int x = base + i;
-        if (x < M) {
-            const int r = I.rank[x];
-            c += (r >= 0 && r < l) || I.P.picked[x];
-        }
-    }
-    c = block_sum_ll(c, red);
-    if (threadIdx.x == 0) I.P.tiles[tile] = (int)c;
-}
+// Compaction of {x : rank[x] < l or picked[x]} in ascending order: one
+// workgroup per instance sweeps its points COMPACT_SPAN at a time. Wave w of
+// a sweep owns COMPACT_ROUNDS consecutive groups of 64 points; lane L reads
+// point 64 q + L of group q (coalesced), a ballot per group gives the flags,
+// and popcounts of the ballots give every point's output position.
+constexpr int COMPACT_THREADS = 1024;
+constexpr int COMPACT_ROUNDS = 16;
+constexpr int COMPACT_WAVES = COMPACT_THREADS / 64;
+constexpr int COMPACT_SPAN = COMPACT_THREADS * COMPACT_ROUNDS;
 
-__global__ __launch_bounds__(256) void k_compact_write(BatchView bv) {
-    __shared__ long long red[4];
-    __shared__ int wsum[4];
-    const int b = uniform(find_range(bv.tile_pref, bv.B, (int)blockIdx.x));
-    CInst &I = bv.tab[b];
+__global__ __launch_bounds__(COMPACT_THREADS) void k_compact(BatchView bv) {
+    __shared__ int wsum[COMPACT_WAVES];
+    CInst &I = bv.tab[blockIdx.x];
     const int l = I.front_info[0];
     const int M = I.M, N = I.N;
-    const int tile = (int)blockIdx.x - bv.tile_pref[b];
-    long long before = 0;
-    for (int t = threadIdx.x; t < tile; t += 256) before += I.P.tiles[t];
-    before = block_sum_ll(before, red);
-    // thread t owns TILE/256 = 16 consecutive points
-    constexpr int PER = TILE / 256;
-    const int x0 = tile * TILE + threadIdx.x * PER;
-    int flags = 0, n = 0;
-    for (int q = 0; q < PER; ++q) {
-        const int x = x0 + q;
-        int f = 0;
-        if (x < M) {
-            const int r = I.rank[x];
-            f = (r >= 0 && r < l) || I.P.picked[x];
-        }
-        flags |= f << q;
-        n += f;
-    }
-    const int incl = wave_incl_scan(n);
     const int wv = threadIdx.x >> 6;
-    if (lane_id() == 63) wsum[wv] = incl;
-    __syncthreads();
-    int woff = 0;
-    for (int i = 0; i < wv; ++i) woff += wsum[i];
-    int pos = (int)before + woff + incl - n;
-    for (int q = 0; q < PER; ++q) {
-        if ((flags >> q) & 1) {
-            if (pos < N) I.selected[pos] = x0 + q;
-            ++pos;
+    const int lane = lane_id();
+    int carry = 0;
+    for (int base = 0; base < M; base += COMPACT_SPAN) {
+        const int x0 = base + wv * 64 * COMPACT_ROUNDS + lane;
+        // all loads first, so that they are in flight together
+        int rk[COMPACT_ROUNDS], pk[COMPACT_ROUNDS];
+#pragma unroll
+        for (int q = 0; q < COMPACT_ROUNDS; ++q) {
+            const int x = x0 + 64 * q;
+            rk[q] = x < M ? I.rank[x] : -1;
+            pk[q] = x < M ? I.P.picked[x] : 0;
         }
+        u64 fl[COMPACT_ROUNDS];
+        int n = 0;
+#pragma unroll
+        for (int q = 0; q < COMPACT_ROUNDS; ++q) {
+            fl[q] = ballot((rk[q] >= 0 && rk[q] < l) || pk[q] != 0);
+            n += __popcll(fl[q]);
+        }
+        if (lane == 0) wsum[wv] = n;
+        lds_barrier();
+        int woff = 0, total = 0;
+#pragma unroll
+        for (int v = 0; v < COMPACT_WAVES; ++v) {
+            const int t = wsum[v];
+            woff += v < wv ? t : 0;
+            total += t;
+        }
+        int pos = carry + woff;
+#pragma unroll
+        for (int q = 0; q < COMPACT_ROUNDS; ++q) {
+            if ((fl[q] >> lane) & 1ull) {
+                const int p = pos + mbcnt(fl[q]);
+                if (p < N) I.selected[p] = x0 + 64 * q;
+            }
+            pos += __popcll(fl[q]);
+        }
+        carry += uniform(total);
+        lds_barrier();  // wsum is reused
     }
-    if (tile == I.ntiles - 1 && threadIdx.x == 255) {
-        if (pos != N) atomicOr(&I.P.ctrl->status, ST_INTERNAL);
-    }
+    if (threadIdx.x == 0 && carry != N) atomicOr(&I.P.ctrl->status, ST_INTERNAL);
 }
 
 hipError_t launch_niche(const HostPlan &hp, const BatchView &bv, hipStream_t s) {
@@ -509,8 +502,7 @@ hipError_t launch_niche(const HostPlan &hp, const BatchView &bv, hipStream_t s) 
     NSGA3_LAUNCH("niche_plan", k_niche_plan, dim3(hp.B), dim3(PLAN_THREADS), 0, s, bv);
     NSGA3_LAUNCH("niche_scatter", k_niche_scatter, dim3(pblocks), dim3(256), 0, s, bv);
     NSGA3_LAUNCH("niche_pick", k_niche_pick, dim3((unsigned)(hp.nref / 4)), dim3(256), 0, s, bv);
-    NSGA3_LAUNCH("compact_count", k_compact_count, dim3(hp.ntile), dim3(256), 0, s, bv);
-    NSGA3_LAUNCH("compact_write", k_compact_write, dim3(hp.ntile), dim3(256), 0, s, bv);
+    NSGA3_LAUNCH("compact", k_compact, dim3(hp.B), dim3(COMPACT_THREADS), 0, s, bv);
     return hipGetLastError();
 }
 

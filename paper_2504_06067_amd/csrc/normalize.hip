@@ -10,13 +10,18 @@
 //                   S_t index list (order irrelevant to every result); in a
 //                   whole selection also prepares the association outputs
 //   k_norm_extreme  per-axis ASF argmin over S_t as a 64-bit (value, index) min
-//   k_norm_solve    one wave per instance: FP64 elimination, degeneracy tests
-//   k_norm_apply    Fn = (f - z) * (1 / a) over S_t
+//   k_norm_solve    one wave per instance (one launch per m): FP64
+//                   elimination, degeneracy tests
+//   k_norm_apply    Fn = (f - z) * (1 / a) over S_t (stage call; a whole
+//                   selection forms Fn in the association sweep)
 #include "nsga3_internal.h"
 
 namespace nsga3 {
 
 __global__ __launch_bounds__(256) void k_norm_reduce(BatchView bv) {
+    __shared__ unsigned s_lo[4][NSGA3_MAX_OBJECTIVES], s_hi[4][NSGA3_MAX_OBJECTIVES];
+    __shared__ int s_cnt[4];
+    __shared__ int s_base;
     const Local L = locate(bv.pt_pref, bv.B);
     CInst &I = bv.tab[L.b];
     const int x = L.i, M = I.M, m = I.m;
@@ -31,22 +36,35 @@ __global__ __launch_bounds__(256) void k_norm_reduce(BatchView bv) {
             I.dist[x] = -1.0f;
         }
     }
-    const u64 bal = ballot(in);
-    if (bal == 0) return;
+    // per-wave, then per-block reductions: one atomic per block and quantity
     const int lane = lane_id();
-    int base = 0;
-    if (lane == 0) base = atomicAdd(&ctrl->list_count, __popcll(bal));
-    base = __shfl(base, 0, 64);
-    if (in) I.P.list[base + mbcnt(bal)] = x;
+    const int wv = threadIdx.x >> 6;
+    const u64 bal = ballot(in);
+    if (lane == 0) s_cnt[wv] = __popcll(bal);
     for (int k = 0; k < m; ++k) {
         const float v = in ? I.F[(size_t)x * m + k] : 0.0f;
         const unsigned lo = wave_min_u32(in ? f2ord(v) : 0xffffffffu);
         const unsigned hi = wave_max_u32(in ? f2ord(v) : 0u);
         if (lane == 0) {
-            atomicMin(&ctrl->zmin_enc[k], lo);
-            atomicMax(&ctrl->fmax_enc[k], hi);
+            s_lo[wv][k] = lo;
+            s_hi[wv][k] = hi;
         }
     }
+    lds_barrier();
+    const int total = uniform(s_cnt[0] + s_cnt[1] + s_cnt[2] + s_cnt[3]);
+    if (total == 0) return;  // block-uniform
+    if (threadIdx.x == 0) s_base = atomicAdd(&ctrl->list_count, total);
+    if ((int)threadIdx.x < m) {
+        const int k = threadIdx.x;
+        const unsigned lo = min(min(s_lo[0][k], s_lo[1][k]), min(s_lo[2][k], s_lo[3][k]));
+        const unsigned hi = max(max(s_hi[0][k], s_hi[1][k]), max(s_hi[2][k], s_hi[3][k]));
+        atomicMin(&ctrl->zmin_enc[k], lo);
+        atomicMax(&ctrl->fmax_enc[k], hi);
+    }
+    lds_barrier();
+    int off = uniform(s_base);
+    for (int v = 0; v < wv; ++v) off += s_cnt[v];
+    if (in) I.P.list[off + mbcnt(bal)] = x;
 }
 
 // ASF_k(x) = max(f'_k, max_{j != k} 1e6 * f'_j) with f' = f - z >= 0 on S_t,
@@ -90,72 +108,120 @@ __global__ __launch_bounds__(256) void k_norm_extreme(BatchView bv, int gs, int 
     (void)gn;
 }
 
-// One wave per instance; lane 0 does the elimination: E[k][j] = f(e_k)_j - z_j
-// in FP64; solve E b = 1 by Gaussian elimination with partial pivoting
-// (largest |pivot|, least row on ties); a_k = 1 / b_k unless degenerate.
-__global__ void k_norm_solve(BatchView bv) {
-    CInst &I = bv.tab[blockIdx.x];
-    if (threadIdx.x != 0) return;
+// Doubles move between lanes as two 32-bit halves.
+__device__ __forceinline__ double read_lane_f64(double v, int L) {
+    const u64 u = (u64)__double_as_longlong(v);
+    const unsigned lo = __builtin_amdgcn_readlane((unsigned)u, L);
+    const unsigned hi = __builtin_amdgcn_readlane((unsigned)(u >> 32), L);
+    return __longlong_as_double((long long)(((u64)hi << 32) | lo));
+}
+__device__ __forceinline__ double shfl_f64(double v, int src) {
+    const u64 u = (u64)__double_as_longlong(v);
+    const unsigned lo = (unsigned)__shfl((int)(unsigned)u, src, 64);
+    const unsigned hi = (unsigned)__shfl((int)(unsigned)(u >> 32), src, 64);
+    return __longlong_as_double((long long)(((u64)hi << 32) | lo));
+}
+
+// One wave per instance of the m-group order[gs .. gs + gn). E[k][j] =
+// f(e_k)_j - z_j in FP64; E b = 1 is solved by Gaussian elimination with
+// partial pivoting (largest |pivot|, least row on ties), the rows spread over
+// the lanes (lane i holds the row at position i; a swap exchanges two lanes'
+// rows), every product and difference rounded separately; a_k = 1 / b_k
+// unless degenerate.
+template <int MO>
+__global__ __launch_bounds__(64) void k_norm_solve(BatchView bv, int gs) {
+    CInst &I = bv.tab[bv.order[gs + blockIdx.x]];
     Ctrl *ctrl = I.P.ctrl;
-    const int M = I.M, m = I.m;
-    double z[NSGA3_MAX_OBJECTIVES], fmx[NSGA3_MAX_OBJECTIVES], b[NSGA3_MAX_OBJECTIVES];
-    double A[NSGA3_MAX_OBJECTIVES][NSGA3_MAX_OBJECTIVES], r[NSGA3_MAX_OBJECTIVES];
-    double colmax[NSGA3_MAX_OBJECTIVES];
-    int ext[NSGA3_MAX_OBJECTIVES];
-    int degen = 0;
-    for (int k = 0; k < m; ++k) {
-        const float zf = ord2f(ctrl->zmin_enc[k]);
-        z[k] = (double)zf;
-        fmx[k] = (double)ord2f(ctrl->fmax_enc[k]) - z[k];
-        ext[k] = (int)(unsigned)(ctrl->ext_key[k] & 0xffffffffull);
-        if (ext[k] < 0 || ext[k] >= M) { ext[k] = 0; degen = 1; atomicOr(&ctrl->status, ST_INTERNAL); }
-        ctrl->zf[k] = zf;
-        I.ideal[k] = zf;
-        I.extreme[k] = ext[k];
+    const int lane = lane_id();
+    const int M = I.M;
+    // ideal point, extreme indices, per-objective span (lane k: objective k)
+    int bad = 0;
+    double zk = 0.0, fmxk = 0.0;
+    int ek = 0;
+    if (lane < MO) {
+        const float zf = ord2f(ctrl->zmin_enc[lane]);
+        zk = (double)zf;
+        fmxk = (double)ord2f(ctrl->fmax_enc[lane]) - zk;
+        ek = (int)(unsigned)(ctrl->ext_key[lane] & 0xffffffffull);
+        if (ek < 0 || ek >= M) { ek = 0; bad = 1; }
+        ctrl->zf[lane] = zf;
+        I.ideal[lane] = zf;
+        I.extreme[lane] = ek;
     }
-    for (int i = 0; i < m; ++i) {
-        r[i] = 1.0;
-        for (int j = 0; j < m; ++j) A[i][j] = (double)I.F[(size_t)ext[i] * m + j] - z[j];
+    int degen = uniform((int)(ballot(bad != 0) != 0));
+    if (degen && lane == 0) atomicOr(&ctrl->status, ST_INTERNAL);
+    // row i of E in lane i: A[j] = f(e_i)_j - z_j, right-hand side 1
+    double A[MO];
+    double rhs = 1.0;
+#pragma unroll
+    for (int j = 0; j < MO; ++j) {
+        const double zj = read_lane_f64(zk, j);
+        A[j] = lane < MO ? (double)I.F[(size_t)ek * MO + j] - zj : 0.0;
     }
-    for (int j = 0; j < m; ++j) {
-        colmax[j] = 0.0;
-        for (int i = 0; i < m; ++i) colmax[j] = fmax(colmax[j], fabs(A[i][j]));
+    // largest |entry| per column of the original matrix
+    double colmax[MO];
+#pragma unroll
+    for (int j = 0; j < MO; ++j) {
+        const u64 key = lane < MO ? (u64)__double_as_longlong(fabs(A[j])) : 0ull;
+        colmax[j] = __longlong_as_double((long long)wave_max_u64(key));
     }
-    for (int c = 0; c < m && !degen; ++c) {
-        int piv = c;
-        for (int i = c + 1; i < m; ++i)
-            if (fabs(A[i][c]) > fabs(A[piv][c])) piv = i;
-        if (colmax[c] == 0.0 || fabs(A[piv][c]) < 1e-10 * colmax[c]) { degen = 1; break; }
+#pragma unroll
+    for (int c = 0; c < MO; ++c) {
+        if (degen) break;
+        // pivot: largest |A[i][c]| over positions i >= c, least position on ties
+        const bool cand = lane >= c && lane < MO;
+        const u64 key = cand ? (u64)__double_as_longlong(fabs(A[c])) : 0ull;
+        const u64 best = wave_max_u64(key);
+        const int piv = __ffsll((long long)ballot(cand && key == best)) - 1;
+        const double pv = __longlong_as_double((long long)best);
+        if (colmax[c] == 0.0 || pv < 1e-10 * colmax[c]) {
+            degen = 1;
+            break;
+        }
         if (piv != c) {
-            for (int j = 0; j < m; ++j) { double t = A[c][j]; A[c][j] = A[piv][j]; A[piv][j] = t; }
-            double t = r[c]; r[c] = r[piv]; r[piv] = t;
+            const int src = lane == c ? piv : (lane == piv ? c : lane);
+#pragma unroll
+            for (int j = 0; j < MO; ++j) A[j] = shfl_f64(A[j], src);
+            rhs = shfl_f64(rhs, src);
         }
-        for (int i = c + 1; i < m; ++i) {
-            const double f = A[i][c] / A[c][c];
-            for (int j = c; j < m; ++j) A[i][j] = __dsub_rn(A[i][j], __dmul_rn(f, A[c][j]));
-            r[i] = __dsub_rn(r[i], __dmul_rn(f, r[c]));
+        const double acc = read_lane_f64(A[c], c);
+        const double rc = read_lane_f64(rhs, c);
+        const bool below = lane > c && lane < MO;
+        const double f = below ? A[c] / acc : 0.0;
+#pragma unroll
+        for (int j = c; j < MO; ++j) {
+            const double acj = read_lane_f64(A[j], c);
+            if (below) A[j] = __dsub_rn(A[j], __dmul_rn(f, acj));
         }
+        if (below) rhs = __dsub_rn(rhs, __dmul_rn(f, rc));
     }
+    double b[MO];
     if (!degen) {
-        for (int i = m - 1; i >= 0; --i) {
-            double s = r[i];
-            for (int j = i + 1; j < m; ++j) s = __dsub_rn(s, __dmul_rn(A[i][j], b[j]));
-            b[i] = s / A[i][i];
+#pragma unroll
+        for (int i = MO - 1; i >= 0; --i) {
+            double s = read_lane_f64(rhs, i);
+#pragma unroll
+            for (int j = i + 1; j < MO; ++j) s = __dsub_rn(s, __dmul_rn(read_lane_f64(A[j], i), b[j]));
+            b[i] = s / read_lane_f64(A[i], i);
         }
     }
-    double a[NSGA3_MAX_OBJECTIVES];
-    for (int k = 0; k < m && !degen; ++k) {
+    // intercepts, or the per-objective maximum when degenerate
+    double ak = 1.0;
+#pragma unroll
+    for (int k = 0; k < MO; ++k) {
+        if (degen) break;
+        const double fk = read_lane_f64(fmxk, k);
         if (!(b[k] > 0.0)) { degen = 1; break; }
-        a[k] = 1.0 / b[k];
-        if (!isfinite(a[k]) || a[k] < 1e-6 * fmx[k]) { degen = 1; break; }
+        const double a = 1.0 / b[k];
+        if (!isfinite(a) || a < 1e-6 * fk) { degen = 1; break; }
+        if (k == lane) ak = a;
     }
-    if (degen)
-        for (int k = 0; k < m; ++k) a[k] = fmx[k] > 0.0 ? fmx[k] : 1.0;
-    for (int k = 0; k < m; ++k) {
-        I.intercept[k] = a[k];
-        ctrl->recip[k] = (float)(1.0 / a[k]);
+    if (degen) ak = fmxk > 0.0 ? fmxk : 1.0;
+    if (lane < MO) {
+        I.intercept[lane] = ak;
+        ctrl->recip[lane] = (float)(1.0 / ak);
     }
-    *I.degenerate = degen;
+    if (lane == 0) *I.degenerate = degen;
 }
 
 __global__ __launch_bounds__(256) void k_norm_apply(BatchView bv) {
@@ -187,8 +253,25 @@ hipError_t launch_normalize(const HostPlan &hp, const BatchView &bv, hipStream_t
         }
 #undef NSGA3_EXT_CASE
     }
-    NSGA3_LAUNCH("norm_solve", k_norm_solve, dim3(hp.B), dim3(64), 0, s, bv);
-    NSGA3_LAUNCH("norm_apply", k_norm_apply, dim3(pblocks), dim3(256), 0, s, bv);
+    for (int g = 0; g < hp.ngroups; ++g) {
+        const unsigned gn = (unsigned)(hp.grp_start[g + 1] - hp.grp_start[g]);
+#define NSGA3_SOLVE_CASE(MO)                                                                   \
+    case MO:                                                                                   \
+        NSGA3_LAUNCH("norm_solve", k_norm_solve<MO>, dim3(gn), dim3(64), 0, s, bv,             \
+                     hp.grp_start[g]);                                                         \
+        break;
+        switch (hp.grp_m[g]) {
+            NSGA3_SOLVE_CASE(2) NSGA3_SOLVE_CASE(3) NSGA3_SOLVE_CASE(4) NSGA3_SOLVE_CASE(5)
+            NSGA3_SOLVE_CASE(6) NSGA3_SOLVE_CASE(7) NSGA3_SOLVE_CASE(8) NSGA3_SOLVE_CASE(9)
+            NSGA3_SOLVE_CASE(10) NSGA3_SOLVE_CASE(11) NSGA3_SOLVE_CASE(12) NSGA3_SOLVE_CASE(13)
+            NSGA3_SOLVE_CASE(14) NSGA3_SOLVE_CASE(15) NSGA3_SOLVE_CASE(16)
+            default: return hipErrorInvalidValue;
+        }
+#undef NSGA3_SOLVE_CASE
+    }
+    // a whole selection forms Fn inside the association sweep instead
+    if (!(bv.run & RUN_ASSOC))
+        NSGA3_LAUNCH("norm_apply", k_norm_apply, dim3(pblocks), dim3(256), 0, s, bv);
     return hipGetLastError();
 }
 

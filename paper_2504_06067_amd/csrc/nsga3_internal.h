@@ -63,15 +63,17 @@ struct Ctrl {
 constexpr int PEEL_SHARDS = 32;
 constexpr int PEEL_STRIDE = 32;  // u64 words between counters
 constexpr int PEEL_SLOT = (PEEL_SHARDS + 1) * PEEL_STRIDE;
-constexpr int ALIVE_PAD = 16;    // u64 words per alive word (one 128-byte line)
+// words per slot of the alive ring: W rounded up to whole 128-byte lines
+constexpr int alive_slot_words(int W) { return (W + 15) & ~15; }
 constexpr int PT_ALIGN = 256;    // per-instance point and reference ranges are padded to this
-constexpr int COMPACT_TILE = 4096;  // points per output-compaction tile
+constexpr int TICKET_SHARDS = 32;   // peel chunk-claim counters of a batch
+constexpr int TICKET_STRIDE = 32;   // u64 words between them (256 bytes)
 
 // Byte offsets of one instance's workspace regions (all 256-byte aligned).
 struct Layout {
     int M, m, H, N, Mp, W, Hp, ns;
-    size_t ctrl, ft, nd, mask, rowm, wit, alive, facc, list, fn, rank, pi, dist, akey, wn,
-        rho, cnt, off, fill, tpick, members, picked, remain, tiles, total;
+    size_t ctrl, ft, nd, mask, alive, facc, list, fn, rank, pi, dist, akey, wn,
+        rho, cnt, off, fill, tpick, members, picked, remain, total;
 };
 
 Layout make_layout(int M, int m, int H, int N);
@@ -81,8 +83,6 @@ struct Ptrs {
     float *ft;
     int *nd;
     u64 *mask;
-    u64 *rowm;
-    int *wit;
     u64 *alive;
     u64 *facc;
     int *list;
@@ -93,7 +93,6 @@ struct Ptrs {
     float *wn;
     int *rho, *cnt, *off, *fill, *tpick, *members, *picked;
     u64 *remain;
-    int *tiles;
 };
 
 Ptrs carve(const Layout &L, void *ws);
@@ -118,7 +117,6 @@ struct Inst {
     int n_stop;
     int G;              // dominance: column tiles per work item
     int R, nslice;      // association: references per slice, slices
-    int ntiles;         // compaction tiles
 };
 
 // Descriptor memory (the batch header) is written by a call's first kernels
@@ -137,11 +135,10 @@ struct BatchView {
     const NSGA3_RO int *pt_pref;
     const NSGA3_RO int *ref_pref;
     const NSGA3_RO int *chunk_pref;
-    const NSGA3_RO int *tile_pref;
     const NSGA3_RO int *order;
     const NSGA3_RO long long *dom_pref;
     const NSGA3_RO long long *asc_pref;
-    u64 *ticket;        // batch-level peel ticket counter
+    u64 *ticket;        // batch-level peel chunk-claim counters (TICKET_SHARDS)
     int B;
     int run;            // RUN_* flags of this call
 };
@@ -201,6 +198,14 @@ __device__ __forceinline__ u64 uniform(u64 v) {
     return ((u64)hi << 32) | lo;
 }
 __device__ __forceinline__ long long uniform(long long v) { return (long long)uniform((u64)v); }
+
+// Workgroup barrier that orders LDS accesses only: unlike __syncthreads it
+// does not wait for this wave's global stores to complete.
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
 
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
@@ -305,7 +310,7 @@ Dev device_info();
 // Host-side plan of one call: totals and the m-groups of the batch.
 struct HostPlan {
     int B;
-    int npt, nref, nchunk, ntile;
+    int npt, nref, nchunk;
     int ngroups;
     int grp_m[NSGA3_MAX_OBJECTIVES + 1];
     int grp_start[NSGA3_MAX_OBJECTIVES + 2];       // range of `order` per group

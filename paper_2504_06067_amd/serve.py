@@ -167,32 +167,58 @@ def _evo_slot(e, run, mode):
         e.generation = run.g + 1
 
 
+class Lane:
+    """One continuous batch on its own HIP stream (default priority)."""
+
+    def __init__(self, device, max_active, stream=None):
+        self.stream = stream if stream is not None else torch.cuda.Stream(device)
+        self.handle = ctypes.c_void_p(self.stream.cuda_stream)
+        self.max_active = max_active
+        self.active = []
+        self.newly = []
+        self.inflight = collections.deque()
+        self.evo_buf = torch.empty(nsga3.evolve_workspace_bytes(max_active), dtype=torch.uint8,
+                                   device=device)
+        self.hdr = nsga3.Workspace(device)
+
+
 class Server:
-    """Runs a request trace. mode "batched": continuous batching; mode
-    "plain": one request at a time with the plain per-instance calls."""
+    """Runs a request trace.
+
+    mode "batched": continuous batching. Admitted runs go to a lane by size
+    (2N below each of `lanes` thresholds, then the rest); each lane is one
+    continuous batch on its own stream, so small runs are not paced by the
+    generations of large ones while the GPU overlaps the lanes' kernels.
+    mode "plain": one request at a time, plain per-instance calls, one stream."""
 
     def __init__(self, device="cuda:0", budget=DEFAULT_BUDGET, mode="batched",
-                 max_batch=nsga3.MAX_BATCH, depth=2):
+                 max_batch=nsga3.MAX_BATCH, depth=2, lanes=(8192, 32768)):
         if mode not in ("batched", "plain"):
             raise ValueError(mode)
         self.device = torch.device(device)
         self.mode = mode
         self.plain = mode == "plain"
-        self.max_active = 1 if self.plain else max_batch
         self.depth = depth
         self.pool = Pool(budget, self.device)
-        self.evo_buf = torch.empty(nsga3.evolve_workspace_bytes(self.max_active),
-                                   dtype=torch.uint8, device=self.device)
-        self.hdr = nsga3.Workspace(self.device)
+        self.bounds = () if self.plain else tuple(sorted(lanes))
+        cap = 1 if self.plain else max_batch
+        self.lanes = [Lane(self.device, cap) for _ in range(len(self.bounds) + 1)]
+
+    def _lane_of(self, M):
+        for i, b in enumerate(self.bounds):
+            if M < b:
+                return self.lanes[i]
+        return self.lanes[-1]
 
     # -- launches -------------------------------------------------------
-    def _evolve(self, runs, mode, stream):
+    def _evolve(self, lane, runs, mode):
         arr = (nsga3.EvolveSlot * len(runs))()
         for e, r in zip(arr, runs):
             _evo_slot(e, r, mode)
-        nsga3.evolve_batched(arr, self.evo_buf, stream=stream)
+        nsga3.evolve_batched(arr, lane.evo_buf, stream=lane.handle)
 
-    def _select(self, runs, stream):
+    def _select(self, lane, runs):
+        stream = lane.handle
         if self.plain:
             for r in runs:
                 req = r.req
@@ -217,35 +243,67 @@ class Server:
         nbytes = int(nsga3.lib().nsga3_batched_workspace_bytes(arr, len(runs)))
         if nbytes == 0:
             raise nsga3.Nsga3Error(nsga3.EINVAL, "nsga3_batched_workspace_bytes")
-        buf = self.hdr.get(nbytes)
+        buf = lane.hdr.get(nbytes)
         nsga3._check(nsga3.lib().nsga3_select_batched(arr, len(runs), nsga3._ptr(buf), buf.numel(),
                                                       stream), "nsga3_select_batched")
+
+    def _tick(self, lane, pending):
+        """Enqueue one generation of every run of the lane (on its stream)."""
+        if lane.newly:
+            self._evolve(lane, lane.newly, nsga3.EVOLVE_INIT)
+            lane.newly = []
+        self._evolve(lane, lane.active, nsga3.EVOLVE_GENERATION)
+        self._select(lane, lane.active)
+        for r in lane.active:
+            r.g += 1
+            r.cur ^= 1
+            r.has_sel = True
+        done = [r for r in lane.active if r.g == r.req["generations"]]
+        if done:
+            self._evolve(lane, done, nsga3.EVOLVE_POPULATION)
+            for r in done:
+                hx = torch.empty(r.Xo.numel(), dtype=torch.float32, pin_memory=True)
+                hf = torch.empty(r.Fo.numel(), dtype=torch.float32, pin_memory=True)
+                hs = torch.empty(1, dtype=torch.int32, pin_memory=True)
+                hx.copy_(r.Xo, non_blocking=True)
+                hf.copy_(r.Fo, non_blocking=True)
+                # status word of the run's last selection (start of its region)
+                hs.copy_(r.ws[:4].view(torch.int32), non_blocking=True)
+                ev = torch.cuda.Event(enable_timing=True)
+                ev.record(lane.stream)
+                pending.append((ev, r, hx, hf, hs))
+            lane.active = [r for r in lane.active if r.g < r.req["generations"]]
+        ev = torch.cuda.Event()
+        ev.record(lane.stream)
+        lane.inflight.append(ev)
 
     # -- the loop -------------------------------------------------------
     def run(self, trace, realtime=True):
         """Serve `trace` (list of request dicts with arrival times in
-        seconds). Returns {rid: dict(X, F, latency_s, done_s)} plus a summary
-        under key None."""
+        seconds). Returns {rid: dict(X, F, latency_s, done_s, status)} plus a
+        summary under key None."""
         dev = self.device
         torch.cuda.synchronize(dev)
-        cs = torch.cuda.current_stream(dev)
-        stream = ctypes.c_void_p(cs.cuda_stream)
         queue = collections.deque(sorted(trace, key=lambda q: (q["arrival"], q["rid"])))
-        active, inflight, results = [], collections.deque(), {}
-        pending = []  # (event, run, host X, host F)
+        results, pending = {}, []
         t_ev = torch.cuda.Event(enable_timing=True)
-        t_ev.record(cs)
+        t_ev.record(torch.cuda.current_stream(dev))
         t0 = time.perf_counter()
-        ticks = 0
-        peak_active = 0
-        peak_bytes = 0
+        ticks = peak_active = peak_bytes = 0
 
         def now():
             return time.perf_counter() - t0 if realtime else float("inf")
 
         def collect(block):
-            while pending and (block or pending[0][0].query()):
-                ev, run, hx, hf, hs = pending.pop(0)
+            # results of finished runs; their memory returns to the pool only
+            # now, after the run's last kernels and copies completed (lanes
+            # run on different streams)
+            keep = []
+            for item in pending:
+                ev, run, hx, hf, hs = item
+                if not (block or ev.query()):
+                    keep.append(item)
+                    continue
                 ev.synchronize()
                 done = t_ev.elapsed_time(ev) / 1e3
                 req = run.req
@@ -253,67 +311,54 @@ class Server:
                                            F=hf.numpy().reshape(req["N"], req["m"]),
                                            done_s=done, latency_s=done - req["arrival"],
                                            status=nsga3.status_from_bits(int(hs[0])))
+                self.pool.release(run.off, run.nbytes)
+            pending[:] = keep
 
-        while queue or active:
+        def busy():
+            return any(lane.active for lane in self.lanes)
+
+        while queue or busy() or pending:
             # admission: arrived requests, in order, while memory and slots allow
-            newly = []
-            while queue and queue[0]["arrival"] <= now() and len(active) < self.max_active:
+            while queue and queue[0]["arrival"] <= now():
                 q = queue[0]
+                lane = self._lane_of(q["M"])
+                if len(lane.active) >= lane.max_active:
+                    break
                 lay, nb = slot_layout(q["M"], q["m"], len(q["Z"]), q["d"], self.plain)
                 if nb > self.pool.size:
                     queue.popleft()
-                    results[q["rid"]] = dict(status=nsga3.EWORKSPACE, latency_s=None)
+                    results[q["rid"]] = dict(status=nsga3.EWORKSPACE, latency_s=None, done_s=None)
                     continue
                 off = self.pool.alloc(nb)
                 if off is None:
                     break
                 queue.popleft()
-                run = Run(q, self.pool, off, lay)
+                with torch.cuda.stream(lane.stream):
+                    run = Run(q, self.pool, off, lay)
                 run.nbytes = nb
-                newly.append(run)
-                active.append(run)
-            if not active:
-                collect(False)
-                if queue:
+                lane.newly.append(run)
+                lane.active.append(run)
+            n_active = sum(len(lane.active) for lane in self.lanes)
+            peak_active = max(peak_active, n_active)
+            peak_bytes = max(peak_bytes, self.pool.used())
+
+            progressed = False
+            for lane in self.lanes:
+                while lane.inflight and lane.inflight[0].query():
+                    lane.inflight.popleft()
+                if lane.active and len(lane.inflight) < self.depth:
+                    with torch.cuda.stream(lane.stream):
+                        self._tick(lane, pending)
+                    ticks += 1
+                    progressed = True
+            collect(False)
+            if not progressed:
+                if not busy() and not pending and queue:
                     wait = queue[0]["arrival"] - now()
                     if wait > 0:
                         time.sleep(min(wait, 0.002))
-                continue
-            peak_active = max(peak_active, len(active))
-            peak_bytes = max(peak_bytes, self.pool.used())
-
-            # one tick: every resident run advances one generation
-            if newly:
-                self._evolve(newly, nsga3.EVOLVE_INIT, stream)
-            self._evolve(active, nsga3.EVOLVE_GENERATION, stream)
-            self._select(active, stream)
-            for r in active:
-                r.g += 1
-                r.cur ^= 1
-                r.has_sel = True
-            done = [r for r in active if r.g == r.req["generations"]]
-            if done:
-                self._evolve(done, nsga3.EVOLVE_POPULATION, stream)
-                for r in done:
-                    hx = torch.empty(r.Xo.numel(), dtype=torch.float32, pin_memory=True)
-                    hf = torch.empty(r.Fo.numel(), dtype=torch.float32, pin_memory=True)
-                    hs = torch.empty(1, dtype=torch.int32, pin_memory=True)
-                    hx.copy_(r.Xo, non_blocking=True)
-                    hf.copy_(r.Fo, non_blocking=True)
-                    # status word of the run's last selection (start of its region)
-                    hs.copy_(r.ws[:4].view(torch.int32), non_blocking=True)
-                    ev = torch.cuda.Event(enable_timing=True)
-                    ev.record(cs)
-                    pending.append((ev, r, hx, hf, hs))
-                    self.pool.release(r.off, r.nbytes)
-                active = [r for r in active if r.g < r.req["generations"]]
-            ticks += 1
-            ev = torch.cuda.Event()
-            ev.record(cs)
-            inflight.append(ev)
-            while len(inflight) > self.depth:
-                inflight.popleft().synchronize()
-            collect(False)
+                else:
+                    time.sleep(0.00005)
         torch.cuda.synchronize(dev)
         collect(True)
         makespan = max((r["done_s"] for r in results.values() if r.get("done_s") is not None),

@@ -50,11 +50,10 @@ def test_workspace_bytes(lib):
     assert ws(2**20 + 1, 3, 10, 5) == 0  # M too large
     small = ws(184, 3, 91, 92)
     assert small > 0 and small % 256 == 0
-    # the bit-packed dominance matrix dominates: ceil(M/64)^2 * 512 bytes, held
-    # twice (word-major as computed, row-major for the peel's scans)
+    # the bit-packed dominance matrix dominates: ceil(M/64)^2 * 512 bytes
     big = ws(131072, 10, 2002, 65536)
     mask = (131072 // 64) ** 2 * 512
-    assert 2 * mask <= big < 2 * mask * 1.05
+    assert mask <= big < mask * 1.05
 
 
 def test_invalid_arguments_enqueue_nothing(lib):
