@@ -30,6 +30,13 @@
 namespace nsga3 {
 
 constexpr int PLAN_THREADS = 1024;
+constexpr int PLAN_BINS = 4096;         // radix-select bins (12 bits; 256 per wave)
+
+__device__ __forceinline__ u64 read_lane_u64(u64 x, int L) {
+    const unsigned lo = __builtin_amdgcn_readlane((unsigned)x, L);
+    const unsigned hi = __builtin_amdgcn_readlane((unsigned)(x >> 32), L);
+    return ((u64)hi << 32) | lo;
+}
 constexpr int PICK_CAP = 2048;          // segment length kept in LDS by one wave
 
 // Stage call only (a whole selection counts in the association's final pass).
@@ -52,9 +59,9 @@ __global__ __launch_bounds__(256) void k_niche_count(BatchView bv) {
 __device__ __forceinline__ long long block_sum_ll(long long v, long long *red) {
     v = wave_sum(v);
     const int w = threadIdx.x >> 6;
-    __syncthreads();
+    lds_barrier();
     if (lane_id() == 0) red[w] = v;
-    __syncthreads();
+    lds_barrier();
     long long s = 0;
     for (int i = 0; i < (int)(blockDim.x >> 6); ++i) s += red[i];
     return uniform(s);
@@ -67,9 +74,9 @@ constexpr int PLAN_PER = 12;
 __device__ __forceinline__ long long block_max_ll(long long v, long long *red) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v = max(v, (long long)__shfl_xor(v, o, 64));
-    __syncthreads();
+    lds_barrier();
     if (lane_id() == 0) red[threadIdx.x >> 6] = v;
-    __syncthreads();
+    lds_barrier();
     long long m = 0;
     for (int i = 0; i < (int)(blockDim.x >> 6); ++i) m = max(m, red[i]);
     return uniform(m);
@@ -86,9 +93,11 @@ __global__ __launch_bounds__(PLAN_THREADS) void k_niche_plan(BatchView bv) {
     int *tpick = I.P.tpick;
     Ctrl *ctrl = I.P.ctrl;
     __shared__ long long red[PLAN_THREADS / 64];
-    __shared__ int part[PLAN_THREADS];
-    __shared__ unsigned hist[256];
-    __shared__ int s_sel[2];
+    __shared__ unsigned hist[PLAN_BINS];
+    __shared__ int wtot[PLAN_THREADS / 64];
+    __shared__ u64 cand[64];
+    __shared__ u64 cand_thr[1];
+    __shared__ int s_sel[4];
     const int tid = threadIdx.x;
     const int wv = uniform((int)(threadIdx.x >> 6));
     const int lane = lane_id();
@@ -124,25 +133,15 @@ __global__ __launch_bounds__(PLAN_THREADS) void k_niche_plan(BatchView bv) {
         }                                                                      \
     }
 
-    // exclusive scan of c
+    // exclusive scan of c: per wave, then over the wave totals
     int local = 0;
     PLAN_FOR({ (void)rj; local += cj; })
-    part[tid] = local;
-    __syncthreads();
-    if (wv == 0) {
-        // wave 0 scans the 1024 partial sums, 16 per lane
-        int s = 0;
-        for (int q = 0; q < 16; ++q) s += part[lane * 16 + q];
-        const int incl = wave_incl_scan(s);
-        int run = incl - s;
-        for (int q = 0; q < 16; ++q) {
-            const int v = part[lane * 16 + q];
-            part[lane * 16 + q] = run;
-            run += v;
-        }
-    }
-    __syncthreads();
-    int run = part[tid];
+    const int wincl = wave_incl_scan(local);
+    if (lane == 63) wtot[wv] = wincl;
+    lds_barrier();
+    int run = wincl - local;
+    for (int v = 0; v < wv; ++v) run += wtot[v];
+    lds_barrier();  // wtot is reused below
     long long hi_local = 0;
     PLAN_FOR({
         off[j] = run;
@@ -185,9 +184,12 @@ __global__ __launch_bounds__(PLAN_THREADS) void k_niche_plan(BatchView bv) {
     const long long tsize = block_sum_ll((long long)tcount, red);
 
     // the r least tag-1 keys of T = {j : rho_j <= L* < rho_j + c_j} get one more
-    // pick: radix select (8 bits per pass, most significant first) of the r-th
-    // least key; keys of distinct references differ (sm64 is a bijection)
-    u64 prefix = ~0ull;  // r == |T|: every key qualifies
+    // pick. The r-th least key is found by radix select, 12 bits per pass from
+    // the top; as soon as the keys left in the chosen bin are at most 64, one
+    // wave ranks them exactly. Keys of distinct references differ (sm64 is a
+    // bijection).
+    u64 prefix = 0;
+    const bool every = r >= tsize;  // r == |T|: every key of T qualifies
     if (r > 0 && r < tsize) {
         u64 kc[PLAN_PER];
 #pragma unroll
@@ -197,61 +199,99 @@ __global__ __launch_bounds__(PLAN_THREADS) void k_niche_plan(BatchView bv) {
             if (cached && j < b1 && cc[q] > 0 && rc[q] <= Ls && Ls < rc[q] + cc[q])
                 kc[q] = tie_key(seed, 1u, (unsigned)j, (unsigned)Ls);
         }
+        // calls f(key) for every key of T owned by this thread
+#define PLAN_KEYS(BODY)                                                                       \
+    if (cached) {                                                                             \
+        _Pragma("unroll") for (int q = 0; q < PLAN_PER; ++q) {                                \
+            const int j = b0 + q;                                                             \
+            if (j < b1 && cc[q] > 0 && rc[q] <= Ls && Ls < rc[q] + cc[q]) {                   \
+                const u64 key = kc[q];                                                        \
+                BODY                                                                          \
+            }                                                                                 \
+        }                                                                                     \
+    } else {                                                                                  \
+        for (int j = b0; j < b1; ++j) {                                                       \
+            if (!(cnt[j] > 0 && rho[j] <= Ls && Ls < rho[j] + cnt[j])) continue;              \
+            const u64 key = tie_key(seed, 1u, (unsigned)j, (unsigned)Ls);                     \
+            BODY                                                                              \
+        }                                                                                     \
+    }
         prefix = 0;
         u64 pmask = 0;
         int need = r;
-        for (int pass = 0; pass < 8; ++pass) {
-            const int shift = 56 - 8 * pass;
-            for (int q = tid; q < 256; q += PLAN_THREADS) hist[q] = 0;
-            __syncthreads();
-            if (cached) {
+        int left = (int)tsize;  // keys matching the prefix
+        for (int shift = 52; left > 64; shift = shift >= 12 ? shift - 12 : 0) {
+            const int bits = shift >= 4 ? 12 : 4;
+            const unsigned dmask = (1u << bits) - 1u;
+            for (int q = tid; q < PLAN_BINS; q += PLAN_THREADS) hist[q] = 0;
+            lds_barrier();
+            PLAN_KEYS({
+                if ((key & pmask) == prefix) atomicAdd(&hist[(key >> shift) & dmask], 1u);
+            })
+            lds_barrier();
+            // wave w scans bins 256w .. 256w + 255 (four per lane)
+            int h[4], sum = 0;
 #pragma unroll
-                for (int q = 0; q < PLAN_PER; ++q) {
-                    const int j = b0 + q;
-                    const bool inT = j < b1 && cc[q] > 0 && rc[q] <= Ls && Ls < rc[q] + cc[q];
-                    if (inT && (kc[q] & pmask) == prefix)
-                        atomicAdd(&hist[(kc[q] >> shift) & 255u], 1u);
-                }
-            } else {
-                for (int j = b0; j < b1; ++j) {
-                    const bool inT = cnt[j] > 0 && rho[j] <= Ls && Ls < rho[j] + cnt[j];
-                    if (!inT) continue;
-                    const u64 kj = tie_key(seed, 1u, (unsigned)j, (unsigned)Ls);
-                    if ((kj & pmask) == prefix) atomicAdd(&hist[(kj >> shift) & 255u], 1u);
-                }
-            }
-            __syncthreads();
-            if (wv == 0) {
-                // lane L holds bins 4L..4L+3; find the bin where the running
-                // count first reaches `need`
-                int h[4], sum = 0;
-#pragma unroll
-                for (int q = 0; q < 4; ++q) { h[q] = (int)hist[4 * lane + q]; sum += h[q]; }
-                const int incl = wave_incl_scan(sum);
-                const u64 reach = ballot(incl >= need);
-                const int L = reach ? __ffsll((long long)reach) - 1 : 63;
-                int acc = uniform(__builtin_amdgcn_readlane(incl - sum, L));
-                int d = 4 * L + 3;
+            for (int q = 0; q < 4; ++q) { h[q] = (int)hist[wv * 256 + 4 * lane + q]; sum += h[q]; }
+            const int incl = wave_incl_scan(sum);
+            if (lane == 63) wtot[wv] = incl;
+            lds_barrier();
+            int before = 0;
+            for (int v = 0; v < wv; ++v) before += wtot[v];
+            before = uniform(before);
+            const int mine = uniform(__builtin_amdgcn_readlane(incl, 63));
+            if (before < need && need <= before + mine) {
+                const u64 reach = ballot(before + incl >= need);
+                const int L = __ffsll((long long)reach) - 1;
+                int acc = before + uniform(__builtin_amdgcn_readlane(incl - sum, L));
+                int d = wv * 256 + 4 * L + 3, cnt_d = 0;
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     const int hq = uniform(__builtin_amdgcn_readlane(h[q], L));
-                    if (acc + hq >= need) { d = 4 * L + q; break; }
+                    if (acc + hq >= need) { d = wv * 256 + 4 * L + q; cnt_d = hq; break; }
                     acc += hq;
                 }
-                s_sel[0] = d;
-                s_sel[1] = need - acc;
+                if (lane == 0) {
+                    s_sel[0] = d;
+                    s_sel[1] = need - acc;
+                    s_sel[2] = cnt_d;
+                }
             }
-            __syncthreads();
+            lds_barrier();
             prefix |= (u64)uniform(s_sel[0]) << shift;
-            pmask |= 255ull << shift;
+            pmask |= (u64)dmask << shift;
             need = uniform(s_sel[1]);
-            __syncthreads();
+            left = uniform(s_sel[2]);
+            if (shift == 0) break;  // every bit fixed: the key itself
         }
+        if (pmask != ~0ull) {
+            // at most 64 keys share the prefix: gather them, one wave ranks them
+            if (tid == 0) s_sel[3] = 0;
+            lds_barrier();
+            PLAN_KEYS({
+                if ((key & pmask) == prefix) cand[atomicAdd(&s_sel[3], 1)] = key;
+            })
+            lds_barrier();
+            if (wv == 0) {
+                const int n = uniform(s_sel[3]);
+                const u64 mykey = lane < n ? cand[lane] : ~0ull;
+                int rank = 0;
+                for (int t = 0; t < n; ++t) {
+                    const u64 other = read_lane_u64(mykey, t);
+                    rank += other < mykey;
+                }
+                const u64 hit = ballot(lane < n && rank == need - 1);
+                if (lane == 0) cand_thr[0] = read_lane_u64(mykey, __ffsll((long long)hit) - 1);
+            }
+            lds_barrier();
+            prefix = uniform(cand_thr[0]);
+        }
+#undef PLAN_KEYS
     }
     PLAN_FOR({
         int t = (int)min((long long)cj, max(0ll, (long long)Ls - rj));
         if (r > 0 && cj > 0 && rj <= Ls && Ls < rj + cj &&
-            (prefix == ~0ull || tie_key(seed, 1u, (unsigned)j, (unsigned)Ls) <= prefix))
+            (every || tie_key(seed, 1u, (unsigned)j, (unsigned)Ls) <= prefix))
             t += 1;
         tpick[j] = t;
     })
