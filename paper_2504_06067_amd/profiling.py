@@ -60,13 +60,22 @@ def _mean_for(per, sub):
     return sum(vals) / len(vals), len(vals)
 
 
+def _max_for(per, sub):
+    """The largest dispatch of a matching kernel (the calibration copy among
+    the small copies a run also makes)."""
+    vals = [v for k, vs in per.items() if sub in k for v in vs]
+    if not vals:
+        raise KeyError(f"no dispatch of a kernel matching {sub!r}")
+    return max(vals)
+
+
 def traffic_record(fetch_csv, write_csv, kernel_sub, copy_sub, copy_bytes, command):
     f = counter_per_dispatch(fetch_csv, "FETCH_SIZE")
     w = counter_per_dispatch(write_csv, "WRITE_SIZE")
     kf, nf = _mean_for(f, kernel_sub)
     kw, nw = _mean_for(w, kernel_sub)
-    cf, _ = _mean_for(f, copy_sub)
-    cw, _ = _mean_for(w, copy_sub)
+    cf = _max_for(f, copy_sub)
+    cw = _max_for(w, copy_sub)
     sf = copy_bytes / (cf * 1024.0)
     sw = copy_bytes / (cw * 1024.0)
     return {
