@@ -157,11 +157,12 @@ typedef struct nsga3_instance {
     float *dist;          /* float32[M] (write) or NULL: its perpendicular distance */
     int32_t M, m, H, N;   /* as nsga3_select */
     uint64_t seed;        /* tie-break seed, as nsga3_select */
-    int32_t tile[4];      /* tile parameters, 0 = automatic: [0] column tiles of 64
-                           * points per dominance work item (a power of two, 1..64),
-                           * [1] references per association slice (16..H, a multiple
-                           * of 16, or H); [2], [3] must be 0. Results do not depend
-                           * on them. */
+    int32_t tile[4];      /* tile parameters, 0 = automatic: [0] 64x64 tiles of the
+                           * dominance triangle per work item (1..2^30; automatic:
+                           * 1..3, from the tiles of all instances of equal m),
+                           * [1] references per
+                           * association slice (16..H, a multiple of 16, or H);
+                           * [2], [3] must be 0. Results do not depend on them. */
     void *ws;             /* this instance's own workspace region (256-byte aligned,
                            * at least nsga3_instance_workspace_bytes), or NULL: the
                            * region is carved from the call's workspace */

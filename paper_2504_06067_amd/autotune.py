@@ -1,12 +1,14 @@
 """Autotuner for the per-instance tile parameters of batched selection.
 
 Two parameters shape the work split without changing any result:
-  tile[0]  column tiles of 64 points per dominance work item (a power of two)
+  tile[0]  dominance tiles per work item. Left at 0: the library sizes items from
+           the tiles of the whole launch (all instances of equal m), not from
+           one instance's bucket.
   tile[1]  references per association slice (a multiple of 16, or H)
-For every (m, size class) bucket the tuner times each candidate on a
+For every (m, size class) bucket the tuner times each slice width on a
 synthetic instance of that shape (the large workload's radius law), with HIP
-events around the two kernels they affect, and keeps the fastest. The table
-is JSON, keyed "m:log2(2N)"; ``lookup`` returns the tiles for an instance, or
+events around the association kernel, and keeps the fastest. The table is
+JSON, keyed "m:log2(2N)"; ``lookup`` returns the tiles for an instance, or
 zeros (the library's own choice) when its bucket was not tuned.
 
 Usage (on the GPU):  python -m paper_2504_06067_amd.autotune --out tiles.json
@@ -19,7 +21,6 @@ import os
 _HERE = os.path.dirname(os.path.abspath(__file__))
 TABLE_PATH = os.path.join(_HERE, "tiles.json")
 
-G_CANDIDATES = (1, 2, 4, 8, 16)
 R_CANDIDATES = (32, 64, 128, 256, 512)
 
 _table = None
@@ -88,23 +89,17 @@ def tune(buckets, device="cuda:0", reps=5, seed=0, log=print):
         Z = torch.from_numpy(Zn).to(dev)
         H = len(Zn)
         base = dict(F=F, Z=Z, N=M // 2, seed=seed)
-        best_g, best_gt = 0, float("inf")
-        for G in G_CANDIDATES:
-            bt = nsga3.Batch([dict(base, tile=[G, 0, 0, 0])])
-            t = _time_kernel(bt, ["dominance"], reps)["dominance"]
-            if t < best_gt:
-                best_g, best_gt = G, t
         best_r, best_rt = 0, float("inf")
         for R in R_CANDIDATES + (H,):
             if R > H or (R != H and R % 16):
                 continue
-            bt = nsga3.Batch([dict(base, tile=[best_g, R, 0, 0])])
+            bt = nsga3.Batch([dict(base, tile=[0, R, 0, 0])])
             t = _time_kernel(bt, ["associate"], reps)["associate"]
             if t < best_rt:
                 best_r, best_rt = R, t
         key = bucket(M, m)
-        table[key] = [best_g, best_r]
-        log(f"{key} (2N={M}, H={H}): G={best_g} ({best_gt:.1f} us), R={best_r} ({best_rt:.1f} us)")
+        table[key] = [0, best_r]
+        log(f"{key} (2N={M}, H={H}): R={best_r} ({best_rt:.1f} us)")
         del F, Z
     return table
 
@@ -120,7 +115,8 @@ def main():
     args = ap.parse_args()
     table = tune(DEFAULT_BUCKETS, reps=args.reps)
     with open(args.out, "w") as f:
-        json.dump({"note": "tiles per bucket m:round(log2(2N)) = [dominance tiles per item, "
+        json.dump({"note": "tiles per bucket m:round(log2(2N)) = [dominance tiles per work "
+                           "item (0: the library sizes them from the whole launch), "
                            "references per association slice]; written by "
                            "python -m paper_2504_06067_amd.autotune",
                    "tiles": table}, f, indent=1, sort_keys=True)

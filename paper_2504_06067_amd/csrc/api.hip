@@ -135,11 +135,16 @@ static HeaderLayout header_layout(int B) {
 // batch whole reference sets per wave).
 constexpr long long ASSOC_WAVES = 16384;
 
-// Column tiles per dominance work item when the caller does not choose:
-// small groups balance the triangle's uneven rows better; from about 400
-// words per row on, four tiles amortize each item's setup (measured on the
-// large and many-objective workloads).
-static int dominance_group(int W) { return W <= 400 ? 2 : 4; }
+// Dominance tiles per work item when the caller does not choose. A launch
+// (the instances of equal m) is cut into about DOM_ROUNDS rounds of waves,
+// DOM_WAVES_PER_CU per compute unit (4 SIMDs x 8 waves), with 1 to
+// DOM_MAX_TILES tiles per item: measured on one MI355X, a single round of
+// long items loses 10-25 % to uneven wave placement, and items of 2-3 tiles
+// amortize the per-item setup (one tile per item costs up to 8 % on small
+// triangles, no item size matters on the largest).
+constexpr long long DOM_WAVES_PER_CU = 32;
+constexpr long long DOM_ROUNDS = 3;
+constexpr long long DOM_MAX_TILES = 3;
 
 static int auto_slice(int H, long long sum_W) {
     long long R = (long long)H * sum_W / ASSOC_WAVES;
@@ -182,7 +187,7 @@ struct Plan {
 };
 
 static bool valid_tiles(const int *t, int H) {
-    if (t[0] < 0 || t[0] > 64 || (t[0] & (t[0] - 1)) != 0) return false;
+    if (t[0] < 0 || t[0] > (1 << 30)) return false;
     if (t[1] < 0 || t[1] > H) return false;
     if (t[1] != 0 && t[1] != H && (t[1] < 16 || t[1] % 16 != 0)) return false;
     return t[2] == 0 && t[3] == 0;
@@ -221,7 +226,7 @@ static void plan(std::vector<Spec> &spec, char *ws, int run, Plan &p) {
         I.W = L.W;
         I.Hp = L.Hp;
         I.ns = L.ns;
-        I.G = spec[b].tile[0] > 0 ? spec[b].tile[0] : dominance_group(L.W);
+        I.G = spec[b].tile[0];  // 0: set per launch group below
         I.R = spec[b].tile[1] > 0 ? spec[b].tile[1] : auto_slice(I.H, sum_W);
         I.nslice = (I.H + I.R - 1) / I.R;
         tab[b] = I;
@@ -239,11 +244,8 @@ static void plan(std::vector<Spec> &spec, char *ws, int run, Plan &p) {
     hp.nchunk = chunk[B];
     hp.ngroups = 0;
     hp.max_W = 0;
-    dom[0] = asc[0] = 0;
     for (int i = 0; i < B; ++i) {
         const Inst &I = tab[order[i]];
-        dom[i + 1] = dom[i] + dominance_items(I.W, I.G);
-        asc[i + 1] = asc[i] + (long long)I.W * I.nslice;
         if (I.W > hp.max_W) hp.max_W = I.W;
         if (i == 0 || I.m != tab[order[i - 1]].m) {
             hp.grp_m[hp.ngroups] = I.m;
@@ -252,6 +254,22 @@ static void plan(std::vector<Spec> &spec, char *ws, int run, Plan &p) {
         }
     }
     hp.grp_start[hp.ngroups] = B;
+    const long long dom_waves = DOM_WAVES_PER_CU * device_info().cus;
+    for (int g = 0; g < hp.ngroups; ++g) {
+        long long tiles = 0;
+        for (int i = hp.grp_start[g]; i < hp.grp_start[g + 1]; ++i) tiles += dominance_tiles(tab[order[i]].W);
+        const long long per = DOM_ROUNDS * dom_waves;
+        long long G = (tiles + per / 2) / per;
+        G = G < 1 ? 1 : (G > DOM_MAX_TILES ? DOM_MAX_TILES : G);
+        for (int i = hp.grp_start[g]; i < hp.grp_start[g + 1]; ++i)
+            if (tab[order[i]].G == 0) tab[order[i]].G = (int)G;
+    }
+    dom[0] = asc[0] = 0;
+    for (int i = 0; i < B; ++i) {
+        const Inst &I = tab[order[i]];
+        dom[i + 1] = dom[i] + (dominance_tiles(I.W) + I.G - 1) / I.G;
+        asc[i + 1] = asc[i] + (long long)I.W * I.nslice;
+    }
     for (int g = 0; g <= hp.ngroups; ++g) {
         hp.grp_dom[g] = dom[hp.grp_start[g]];
         hp.grp_asc[g] = asc[hp.grp_start[g]];

@@ -20,10 +20,7 @@
 
 namespace nsga3 {
 
-long long dominance_items(int W, int G_) {
-    const long long G = G_, q = W / G, s = W % G;
-    return (long long)W + G * q * (q - 1) / 2 + q * s;
-}
+long long dominance_tiles(int W) { return (long long)W * (W + 1) / 2; }
 
 __global__ __launch_bounds__(256) void k_init(BatchView bv) {
     CInst &I = bv.tab[blockIdx.x];
@@ -129,10 +126,15 @@ __device__ __forceinline__ unsigned write_lane(unsigned old, unsigned v) {
     return old;
 }
 
-// Work items of block rows 0 .. jb - 1 for G = 2^gsh column tiles per item.
-__device__ __forceinline__ long long items_before(int jb, int gsh) {
-    const long long q = jb >> gsh, s = jb & ((1 << gsh) - 1);
-    return (long long)jb + (((q * (q - 1)) >> 1) << gsh) + q * s;
+// Tiles of the triangle in rows 0 .. jb - 1 (row jb holds tiles ib = 0 .. jb).
+__device__ __forceinline__ long long tri(long long jb) { return jb * (jb + 1) / 2; }
+
+// Row of triangle tile t: the largest jb with tri(jb) <= t.
+__device__ __forceinline__ int row_of(long long t) {
+    long long jb = (long long)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+    while (tri(jb + 1) <= t) ++jb;
+    while (tri(jb) > t) --jb;
+    return (int)jb;
 }
 
 // GW consecutive column values of one objective (one scalar load). The
@@ -201,9 +203,12 @@ __device__ __forceinline__ void dom_tile(std::integer_sequence<int, Gs...>,
 }
 
 // One wave per work item of the instances with m = MO (the group order[gs ..
-// gs + gn)): the 64 points of block row jb sit in the lanes (as the dominated
-// side j); the item sweeps up to G column blocks ib <= jb, reading the
-// column points through the scalar cache.
+// gs + gn)). The item is a run of G consecutive tiles of its instance's
+// triangle in row-major order (row jb: column blocks ib = 0 .. jb), so every
+// item of an instance carries the same work and one round of waves covers a
+// launch. Along a row the 64 points of block jb stay in the lanes (as the
+// dominated side j) and the column points of block ib come through the
+// scalar cache.
 template <int MO>
 __global__ __launch_bounds__(256) void k_dominance(BatchView bv, int gs, int gn,
                                                     long long item0, long long n_items) {
@@ -213,46 +218,46 @@ __global__ __launch_bounds__(256) void k_dominance(BatchView bv, int gs, int gn,
     const int gi = uniform(find_range(bv.dom_pref + gs, gn, gitem));
     CInst &I = bv.tab[bv.order[gs + gi]];
     const long long item = gitem - bv.dom_pref[gs + gi];
-    const int W = I.W, Mp = I.Mp, G = I.G, gsh = __builtin_ctz((unsigned)G);
+    const int W = I.W, Mp = I.Mp;
+    const long long G = I.G, T = tri(W);
     // the objective copy is written by k_prep and only read here: invariant
     // loads, so the column points come through the scalar cache
     const NSGA3_RO float *ft = (const NSGA3_RO float *)I.P.ft;
     u64 *__restrict__ mask = I.P.mask;
     int *__restrict__ nd = I.P.nd;
-    // block row: largest jb with items_before(jb) <= item
-    int lo = 0, hi = W;
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (items_before(mid, gsh) <= item) lo = mid;
-        else hi = mid;
-    }
-    const int jb = lo;
-    const int g = (int)(item - items_before(jb, gsh));
-    const int ib0 = g * G;
-    const int ib1 = min(ib0 + G, jb + 1);
-
-    const size_t jglob = (size_t)jb * 64 + lane;
-    float fj[MO];
+    long long t = item * G;
+    const long long t_end = t + G < T ? t + G : T;
+    int jb = uniform(row_of(t));
+    int ib = (int)(t - tri(jb));
+    constexpr int GW = col_group<MO>();
+    while (t < t_end) {
+        const size_t jglob = (size_t)jb * 64 + lane;
+        float fj[MO];
 #pragma unroll
-    for (int k = 0; k < MO; ++k) fj[k] = ft[((size_t)jb * MO + k) * 64 + lane];
-
-    int cnt_j = 0;
-    for (int ib = ib0; ib < ib1; ++ib) {
-        unsigned a_lo = 0, a_hi = 0, b_lo = 0, b_hi = 0;
-        const NSGA3_RO float *fi = ft + (size_t)ib * MO * 64;
-        constexpr int GW = col_group<MO>();
-        dom_tile<MO, GW>(std::make_integer_sequence<int, 64 / GW>{}, fi, fj, a_lo, a_hi, b_lo, b_hi);
-        const u64 A = ((u64)a_hi << 32) | a_lo;
-        mask[(size_t)ib * Mp + jglob] = A;
-        cnt_j += __popcll(A);
-        if (ib != jb) {
-            const u64 B = ((u64)b_hi << 32) | b_lo;
-            mask[(size_t)jb * Mp + (size_t)ib * 64 + lane] = B;
-            const int c = __popcll(B);
-            if (c) atomicAdd(&nd[ib * 64 + lane], c);
+        for (int k = 0; k < MO; ++k) fj[k] = ft[((size_t)jb * MO + k) * 64 + lane];
+        // tiles of this row within the item
+        const int ib1 = (int)(t_end - t < (long long)(jb + 1 - ib) ? ib + (t_end - t) : jb + 1);
+        int cnt_j = 0;
+        for (; ib < ib1; ++ib) {
+            unsigned a_lo = 0, a_hi = 0, b_lo = 0, b_hi = 0;
+            const NSGA3_RO float *fi = ft + (size_t)ib * MO * 64;
+            dom_tile<MO, GW>(std::make_integer_sequence<int, 64 / GW>{}, fi, fj, a_lo, a_hi, b_lo,
+                             b_hi);
+            const u64 A = ((u64)a_hi << 32) | a_lo;
+            mask[(size_t)ib * Mp + jglob] = A;
+            cnt_j += __popcll(A);
+            if (ib != jb) {
+                const u64 B = ((u64)b_hi << 32) | b_lo;
+                mask[(size_t)jb * Mp + (size_t)ib * 64 + lane] = B;
+                const int c = __popcll(B);
+                if (c) atomicAdd(&nd[ib * 64 + lane], c);
+            }
         }
+        if (cnt_j) atomicAdd(&nd[jglob], cnt_j);
+        t = tri(jb) + ib1;
+        ++jb;
+        ib = 0;
     }
-    if (cnt_j) atomicAdd(&nd[jglob], cnt_j);
 }
 
 // Front peeling.
@@ -303,7 +308,8 @@ __global__ __launch_bounds__(256) void k_dominance(BatchView bv, int gs, int gn,
 constexpr int PEEL_WAVES = 8;
 constexpr int PEEL_OWN_CAP = 1024;
 constexpr int PEEL_LDS_ALIVE = 2048;  // words staged in LDS (M <= 131072)
-constexpr int PEEL_BATCH = 16;        // matrix loads in flight per wave
+constexpr int PEEL_BATCH = 16;        // matrix loads in flight per wave (streamed columns)
+constexpr int PEEL_CACHE_SLOTS = 2;   // owned chunks whose columns stay in registers
 
 __device__ __forceinline__ u64 *peel_slot(u64 *ring, int k) { return ring + (size_t)(k % 3) * PEEL_SLOT; }
 
@@ -331,13 +337,33 @@ __device__ __forceinline__ u64 dead_word(const PeelShared &sh, const u64 *alive_
     return alive_p[w] & ~alive_k[w];
 }
 
+// Column cache of an owned chunk c: its matrix words mask[w * Mp + 64c +
+// lane] for w = wv + q * PEEL_WAVES (q < Q), zero from w = W on, loaded once
+// and held in registers for every later front (the matrix is then read once
+// per chunk instead of once per front).
+template <int Q>
+__device__ __forceinline__ void load_column(const CInst &I, int c, u64 (&col)[Q]) {
+    const int wv = uniform((int)(threadIdx.x >> 6));
+    const u64 *p = I.P.mask + (size_t)c * 64 + lane_id();
+    const int W = I.W;
+    const size_t Mp = (size_t)I.Mp;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const int w = wv + q * PEEL_WAVES;
+        col[q] = w < W ? p[(size_t)w * Mp] : 0ull;
+    }
+}
+
 // Ranks the points of chunk c that are alive at front k and have no alive
 // dominator; publishes the chunk's result. All waves take part.
 // STAGED: the members of front k - 1 are staged in LDS (W <= PEEL_LDS_ALIVE);
 // a compile-time choice, so that no pointer ever selects between LDS and
-// global memory.
-template <bool STAGED>
-__device__ void peel_chunk_impl(CInst &I, int k, int c, PeelShared &sh) {
+// global memory. Q > 0: the chunk's column is in `col` (load_column; needs
+// STAGED and W <= Q * PEEL_WAVES); Q = 0: the column is streamed, BATCH
+// loads in flight per wave.
+template <bool STAGED, int Q, int BATCH>
+__device__ void peel_chunk_impl(CInst &I, int k, int c, PeelShared &sh,
+                                const u64 (&col)[Q > 0 ? Q : 1]) {
     const int lane = lane_id();
     const int wv = uniform((int)(threadIdx.x >> 6));
     const int W = I.W, ns = I.ns;
@@ -358,20 +384,26 @@ __device__ void peel_chunk_impl(CInst &I, int k, int c, PeelShared &sh) {
             for (int w = threadIdx.x; w < W; w += blockDim.x) sh.dead[w] = alive_p[w] & ~alive_k[w];
         lds_barrier();
         if (aw != 0) {
-            // wave wv takes blocks wv, wv + PEEL_WAVES, ...; PEEL_BATCH loads in flight
-            const u64 *__restrict__ col = I.P.mask + (size_t)c * 64 + lane;
-            const size_t Mp = (size_t)I.Mp;
+            // wave wv takes blocks wv, wv + PEEL_WAVES, ...
             int acc = 0;
-            for (int w0 = wv; w0 < W; w0 += PEEL_WAVES * PEEL_BATCH) {
-                u64 x[PEEL_BATCH], d[PEEL_BATCH];
+            if constexpr (Q > 0) {
+                // words from w = W on are zero in the cache
 #pragma unroll
-                for (int q = 0; q < PEEL_BATCH; ++q) {
-                    const int w = w0 + q * PEEL_WAVES;
-                    d[q] = w < W ? dead_word<STAGED>(sh, alive_p, alive_k, w) : 0ull;
-                    x[q] = d[q] ? col[(size_t)w * Mp] : 0ull;
+                for (int q = 0; q < Q; ++q) acc += __popcll(col[q] & sh.dead[wv + q * PEEL_WAVES]);
+            } else {
+                const u64 *__restrict__ src = I.P.mask + (size_t)c * 64 + lane;
+                const size_t Mp = (size_t)I.Mp;
+                for (int w0 = wv; w0 < W; w0 += PEEL_WAVES * BATCH) {
+                    u64 x[BATCH], d[BATCH];
+#pragma unroll
+                    for (int q = 0; q < BATCH; ++q) {
+                        const int w = w0 + q * PEEL_WAVES;
+                        d[q] = w < W ? dead_word<STAGED>(sh, alive_p, alive_k, w) : 0ull;
+                        x[q] = d[q] ? src[(size_t)w * Mp] : 0ull;
+                    }
+#pragma unroll
+                    for (int q = 0; q < BATCH; ++q) acc += __popcll(x[q] & d[q]);
                 }
-#pragma unroll
-                for (int q = 0; q < PEEL_BATCH; ++q) acc += __popcll(x[q] & d[q]);
             }
             sh.part[wv][lane] = acc;
         }
@@ -415,12 +447,20 @@ __device__ void peel_chunk_impl(CInst &I, int k, int c, PeelShared &sh) {
     }
 }
 
+// A chunk whose column is streamed.
+template <int BATCH>
 __device__ __forceinline__ void peel_chunk(CInst &I, int k, int c, PeelShared &sh) {
-    if (uniform(I.W) <= PEEL_LDS_ALIVE) peel_chunk_impl<true>(I, k, c, sh);
-    else peel_chunk_impl<false>(I, k, c, sh);
+    const u64 none[1] = {0ull};
+    if (uniform(I.W) <= PEEL_LDS_ALIVE) peel_chunk_impl<true, 0, BATCH>(I, k, c, sh, none);
+    else peel_chunk_impl<false, 0, BATCH>(I, k, c, sh, none);
 }
 
+// Q > 0: the first PEEL_CACHE_SLOTS chunks a workgroup owns keep their
+// columns in registers (every instance has W <= Q * PEEL_WAVES); further
+// chunks, if any, are streamed.
+template <int Q>
 __global__ __launch_bounds__(64 * PEEL_WAVES) void k_peel(BatchView bv, int nchunk) {
+    constexpr int BATCH = Q > 0 ? 4 : PEEL_BATCH;  // streamed chunks: fewer registers next to a cache
     __shared__ PeelShared sh;
     const int lane = lane_id();
     const int wv = uniform((int)(threadIdx.x >> 6));
@@ -467,7 +507,7 @@ __global__ __launch_bounds__(64 * PEEL_WAVES) void k_peel(BatchView bv, int nchu
         if (t >= (u64)nchunk) break;
         const int b = uniform(find_range(bv.chunk_pref, bv.B, (int)t));
         const int c = (int)t - bv.chunk_pref[b];
-        peel_chunk(bv.tab[b], 0, c, sh);
+        peel_chunk<BATCH>(bv.tab[b], 0, c, sh);
         if (wv == 0) {
             sh.own_b[nown] = b;
             sh.own_c[nown] = c;
@@ -480,6 +520,12 @@ __global__ __launch_bounds__(64 * PEEL_WAVES) void k_peel(BatchView bv, int nchu
     // a workgroup without chunks has nothing left to do; the owners of the
     // chunks report the front fill
     if (nown == 0) return;
+    // the cached columns load while the other chunks of front 0 finish
+    u64 col0[Q > 0 ? Q : 1], col1[Q > 0 ? Q : 1];
+    if constexpr (Q > 0) {
+        load_column<Q>(bv.tab[uniform(sh.own_b[0])], uniform(sh.own_c[0]), col0);
+        if (nown > 1) load_column<Q>(bv.tab[uniform(sh.own_b[1])], uniform(sh.own_c[1]), col1);
+    }
 
     for (int k = 1;; ++k) {
         int active = 0;
@@ -526,7 +572,14 @@ __global__ __launch_bounds__(64 * PEEL_WAVES) void k_peel(BatchView bv, int nchu
                 continue;
             }
             if (wv == 0) sh.own_cum[q] = cum;
-            peel_chunk(I, k, c, sh);
+            if constexpr (Q > 0) {
+                static_assert(PEEL_CACHE_SLOTS == 2, "one branch per cached slot");
+                if (q == 0) peel_chunk_impl<true, Q, BATCH>(I, k, c, sh, col0);
+                else if (q == 1) peel_chunk_impl<true, Q, BATCH>(I, k, c, sh, col1);
+                else peel_chunk<BATCH>(I, k, c, sh);
+            } else {
+                peel_chunk<BATCH>(I, k, c, sh);
+            }
             active = 1;
         }
         lds_barrier();
@@ -559,9 +612,24 @@ hipError_t launch_nd_sort(const HostPlan &hp, const BatchView &bv, hipStream_t s
         }
 #undef NSGA3_DOM_CASE
     }
-    const int cap = 3 * device_info().cus;
+    // Columns stay in registers when every instance's column fits a cache
+    // and two cached chunks per compute unit hold all chunks (one workgroup
+    // per compute unit at that register use); otherwise they are streamed.
+    const int cus = device_info().cus;
+    int q = 0;
+    if (hp.nchunk <= PEEL_CACHE_SLOTS * cus)
+        q = hp.max_W <= 16 * PEEL_WAVES ? 16
+            : hp.max_W <= 32 * PEEL_WAVES ? 32
+            : hp.max_W <= 48 * PEEL_WAVES ? 48 : 0;
+    const int cap = q ? cus : 3 * cus;
     const int peel_blocks = hp.nchunk < cap ? hp.nchunk : cap;
-    NSGA3_LAUNCH("peel", k_peel, dim3(peel_blocks), dim3(64 * PEEL_WAVES), 0, s, bv, hp.nchunk);
+    const dim3 pg(peel_blocks), pb(64 * PEEL_WAVES);
+    switch (q) {
+        case 16: NSGA3_LAUNCH("peel", k_peel<16>, pg, pb, 0, s, bv, hp.nchunk); break;
+        case 32: NSGA3_LAUNCH("peel", k_peel<32>, pg, pb, 0, s, bv, hp.nchunk); break;
+        case 48: NSGA3_LAUNCH("peel", k_peel<48>, pg, pb, 0, s, bv, hp.nchunk); break;
+        default: NSGA3_LAUNCH("peel", k_peel<0>, pg, pb, 0, s, bv, hp.nchunk); break;
+    }
     return hipGetLastError();
 }
 

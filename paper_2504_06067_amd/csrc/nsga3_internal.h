@@ -115,7 +115,7 @@ struct Inst {
     u64 seed;
     int M, m, H, N, Mp, W, Hp, ns;
     int n_stop;
-    int G;              // dominance: column tiles per work item
+    int G;              // dominance: triangle tiles per work item
     int R, nslice;      // association: references per slice, slices
 };
 
@@ -336,6 +336,6 @@ hipError_t launch_niche(const HostPlan &hp, const BatchView &bv, hipStream_t s);
 
 // dominance work items of an instance (waves): block row jb holds
 // floor(jb / G) + 1 items of up to G column tiles each
-long long dominance_items(int W, int G);
+long long dominance_tiles(int W);  // 64x64 tiles of the triangle ib <= jb
 
 }  // namespace nsga3

@@ -114,9 +114,9 @@ def test_batched_workspace_bytes(lib):
     assert f(None, 1) == 0
     assert f(_batch([(5000, 3, 91, 2500)] * 2), 1025) == 0        # B above the limit
     assert f(_batch([(1, 3, 91, 1)]), 1) == 0                     # bad shape
-    for t in ([65], [3], [12], [0, 7], [0, 0, 1], [0, 0, 0, 2], [-1], [0, 96]):
+    for t in ([(1 << 30) + 1], [0, 7], [0, 0, 1], [0, 0, 0, 2], [-1], [0, 96]):
         assert f(_batch([(5000, 3, 91, 2500)], {0: t}), 1) == 0, t
-    for t in ([1], [64, 16], [0, 91], [8, 80]):
+    for t in ([1], [3], [65, 16], [0, 91], [8, 80], [1 << 30]):
         assert f(_batch([(5000, 3, 91, 2500)], {0: t}), 1) > 0, t
 
 

@@ -90,7 +90,7 @@ def test_tile_invariance():
             return H
         return r if r <= H else H
 
-    for g_tile, r_tile in [(1, 16), (4, 0), (64, 32), (2, "H")]:
+    for g_tile, r_tile in [(1, 16), (3, 0), (64, 32), (1000, "H"), (1 << 30, 48)]:
         tiles = [[g_tile, slice_of(q["H"], r_tile), 0, 0] for q in insts]
         got = run_batched(insts, dev, tiles)
         for a, b in zip(base, got):
@@ -173,7 +173,7 @@ def test_status_per_instance():
 def test_batched_rejects_bad_arguments():
     dev = device()
     insts = mixed_instances(4, 2)
-    for tile in ([65, 0, 0, 0], [3, 0, 0, 0], [0, 7, 0, 0], [0, 0, 1, 0], [-1, 0, 0, 0]):
+    for tile in ([(1 << 30) + 1, 0, 0, 0], [0, 7, 0, 0], [0, 0, 1, 0], [-1, 0, 0, 0]):
         with pytest.raises(nsga3.Nsga3Error):
             nsga3.Batch(as_problems(insts, dev, [tile, [0, 0, 0, 0]]))
     bt = nsga3.Batch(as_problems(insts, dev))
