@@ -31,13 +31,7 @@ Layout make_layout(int M, int m, int H, int N) {
     L.ft = take((size_t)m * Mp * 4);
     L.nd = take(Mp * 4);
     L.mask = take(W * Mp * 8);
-    // alive ring: ns slots of W packed words (one slot per front)
-    const size_t slot_bytes = (size_t)alive_slot_words(L.W) * 8;
-    L.ns = (int)((16ull << 20) / slot_bytes);
-    if (L.ns > 254) L.ns = 254;
-    if (L.ns < 8) L.ns = 8;
-    L.alive = take((size_t)L.ns * slot_bytes);
-    L.facc = take(3 * PEEL_SLOT * 8);  // front-peeling counter ring
+    L.ring = take((size_t)PEEL_RING * front_slot_words(L.W) * 8);  // peel front ring
     L.list = take(Mp * 4);
     L.fn = take(Mp * (size_t)m * 4);
     L.rank = take(Mp * 4);
@@ -64,8 +58,7 @@ Ptrs carve(const Layout &L, void *ws) {
     P.ft = (float *)(b + L.ft);
     P.nd = (int *)(b + L.nd);
     P.mask = (u64 *)(b + L.mask);
-    P.alive = (u64 *)(b + L.alive);
-    P.facc = (u64 *)(b + L.facc);
+    P.ring = (u64 *)(b + L.ring);
     P.list = (int *)(b + L.list);
     P.fn = (float *)(b + L.fn);
     P.rank = (int *)(b + L.rank);
@@ -225,7 +218,6 @@ static void plan(std::vector<Spec> &spec, char *ws, int run, Plan &p) {
         I.Mp = L.Mp;
         I.W = L.W;
         I.Hp = L.Hp;
-        I.ns = L.ns;
         I.G = spec[b].tile[0];  // 0: set per launch group below
         I.R = spec[b].tile[1] > 0 ? spec[b].tile[1] : auto_slice(I.H, sum_W);
         I.nslice = (I.H + I.R - 1) / I.R;

@@ -9,7 +9,7 @@
 // Kernels:
 //   k_init       per instance: control block, peel counters, front_info
 //   k_prep       points: tile-major objective copy (+inf padding), finiteness,
-//                dominator counts, ranks, alive set of front 0, niche flags;
+//                dominator counts, ranks, the peel's front ring, niche flags;
 //                references: unit directions and their check, niche counters
 //   k_dominance  triangle of 64x64 tiles; both directions from one set of 2m
 //                compares per pair; fused dominator counts
@@ -43,8 +43,6 @@ __global__ __launch_bounds__(256) void k_init(BatchView bv) {
         ctrl->fmax_enc[t] = 0u;
         ctrl->ext_key[t] = ~0ull;
     }
-    if (bv.run & RUN_ND)
-        for (int i = t; i < 3 * PEEL_SLOT; i += blockDim.x) I.P.facc[i] = 0;
 }
 
 // Grid: [all instances' padded points][all instances' padded references].
@@ -67,9 +65,14 @@ __global__ __launch_bounds__(256) void k_prep(BatchView bv, int npt) {
             I.P.nd[j] = 0;
             if (j < M) I.rank[j] = NSGA3_UNRANKED;
             if ((j & 63) == 0) {
-                const int valid = M - j;
-                I.P.alive[(size_t)(j >> 6)] =
-                    valid >= 64 ? ~0ull : (valid <= 0 ? 0ull : ((1ull << valid) - 1));
+                // no word of the front ring may carry a tag of this call yet
+                u64 *ring = I.P.ring + (size_t)(j >> 5);
+                const size_t sw = (size_t)front_slot_words(I.W);
+#pragma unroll
+                for (int r = 0; r < PEEL_RING; ++r) {
+                    ring[r * sw] = 0ull;
+                    ring[r * sw + 1] = 0ull;
+                }
             }
         }
         if (j < M && (bv.run & RUN_NICHE)) I.P.picked[j] = 0;
@@ -268,73 +271,112 @@ __global__ __launch_bounds__(256) void k_dominance(BatchView bv, int gs, int gn,
 // points whose count is zero. When front k - 1 is known, each chunk subtracts,
 // for every block w of 64 points that lost members to front k - 1, the
 // popcount of (its points' word w of the dominance matrix) AND (those
-// members): one coalesced 512-byte load per block w and wave, all blocks in
-// flight at once, no per-point searching. The peel of an instance stops once
-// its ranked fronts hold n_stop points.
+// members), no per-point searching. The matrix words of a chunk are either
+// held in registers from front 1 on (load_column) or streamed, one coalesced
+// 512-byte load per block w and wave, all blocks in flight at once. The peel
+// of an instance stops once its ranked fronts hold n_stop points.
 //
 // Scheduling. While ranking front 0, workgroups claim chunks (of any
-// instance) from sharded ticket counters until every chunk is claimed; a workgroup
-// then owns its chunks for all later fronts and processes them front by
-// front. Only running workgroups claim, and no workgroup waits before all
-// chunks are claimed and ranked for front 0; later waits are for lower fronts
-// of chunks owned by running workgroups, so every wait ends. A workgroup
-// records at most PEEL_OWN_CAP chunks; if every running workgroup were full
-// the front-0 wait would time out into an error status.
+// instance) from sharded ticket counters until every chunk is claimed; a
+// workgroup then owns its chunks for all later fronts and processes them
+// front by front. Only running workgroups claim, and no workgroup waits
+// before all chunks are claimed and ranked for front 0; later waits are for
+// lower fronts of chunks owned by running workgroups, so every wait ends. A
+// workgroup records at most PEEL_OWN_CAP chunks; if every running workgroup
+// were full the front-1 wait would time out into an error status.
 //
-// Completion. Per front, chunk c adds (points ranked << 32) + 1 to shard
-// counter c % PEEL_SHARDS of its instance; the chunk whose add completes its
-// shard adds the shard's (points << 32) + 1 to the front total, which a
-// waiting workgroup polls with one load (the shards spread the atomics over
-// many addresses, the total keeps the polling to one word). Counters live in
-// a ring of three front slots per instance; each chunk clears its shard of
-// front k + 1's slot (chunk 0 also its total) when it publishes front k:
-// that slot last held front k - 2, whose waits all ended before front k - 1
-// could complete.
+// Publication. When chunk c has ranked its members of front k, it stores them
+// in slot k % PEEL_RING of the instance's front ring as two tagged words (the
+// tag k + 1 in the high 32 bits; the low, then the high 32 bits of the member
+// mask in the low 32 bits), and waits for nothing. A workgroup waiting for
+// front k polls all tagged words of the slot: once every tag reads k + 1, the
+// same loads have delivered the members of front k of every block, and their
+// popcounts give the front's size. A slot is written again (for front
+// k + PEEL_RING) only after front k + PEEL_RING - 1 completed, which needs every
+// owner to have read front k before; the tag tells a stale word from a
+// current one, and the ring is zeroed when the call starts, so no word of an
+// earlier call carries a current tag.
 //
-// Memory ordering. Alive words and counters are written with agent-scope
-// atomic stores, which go to the coherent level; each chunk waits for its
-// stores before its counter add. Waiters poll the counters with relaxed
-// atomic loads. Alive words are then read with ordinary cached loads. The
-// words of one front are packed in their own slot of a ring: a slot is
-// written only while the front before it is processed and read only after
-// that front completed, so no workgroup holds a line of it while it is being
-// written; slots are reused only after `ns` fronts, and then an agent-scope
-// acquire drops stale copies. A chunk's counts are read and written only by
-// wave 0 of its owner, whose publish waits for its stores.
+// Memory ordering. Tagged words are written with agent-scope atomic stores
+// and polled with agent-scope atomic loads, so every read sees the coherent
+// level; an aligned 64-bit store is single-copy atomic, so a word with a
+// current tag carries its current half of the mask. A chunk's counts and its
+// alive mask are read and written only by wave 0 of its owner.
 //
 // Control flow is wave-uniform around every workgroup barrier: wave 0 makes
 // the scheduling decisions with all its lanes and shares them through LDS.
 // Barriers order LDS only (they do not wait for global stores in flight).
 constexpr int PEEL_WAVES = 8;
 constexpr int PEEL_OWN_CAP = 1024;
-constexpr int PEEL_LDS_ALIVE = 2048;  // words staged in LDS (M <= 131072)
+constexpr int PEEL_LDS_ALIVE = 2048;  // blocks whose members are staged in LDS (M <= 131072)
 constexpr int PEEL_BATCH = 16;        // matrix loads in flight per wave (streamed columns)
 constexpr int PEEL_CACHE_SLOTS = 2;   // owned chunks whose columns stay in registers
+constexpr unsigned PEEL_POLLS = 1u << 24;  // polls before a wait gives up (an internal error)
 
-__device__ __forceinline__ u64 *peel_slot(u64 *ring, int k) { return ring + (size_t)(k % 3) * PEEL_SLOT; }
-
-// Alive bitset of front k: slot k % ns of the alive ring (W words, padded to
-// whole 128-byte lines).
-__device__ __forceinline__ u64 *alive_slot(u64 *aring, int W, int ns, int k) {
-    return aring + (size_t)(k % ns) * alive_slot_words(W);
+// Tagged members of front k: slot k % PEEL_RING of the ring (2W words,
+// padded to whole 128-byte lines).
+__device__ __forceinline__ u64 *front_slot(u64 *ring, int W, int k) {
+    return ring + (size_t)(k % PEEL_RING) * front_slot_words(W);
 }
 
 struct PeelShared {
     int own_b[PEEL_OWN_CAP];    // instance of each owned chunk
     int own_c[PEEL_OWN_CAP];    // chunk within its instance
     int own_cum[PEEL_OWN_CAP];  // points in the instance's fronts seen so far (-1: done)
-    u64 dead[PEEL_LDS_ALIVE];   // members of front k - 1, per block of 64 points
+    u64 own_alive[PEEL_OWN_CAP];  // its points not yet ranked
+    u64 dead[PEEL_LDS_ALIVE];   // members of the awaited front, per block of 64 points
     int part[PEEL_WAVES][64];   // per-wave partial decrements of the chunk's counts
+    int red_bad[PEEL_WAVES];    // per-wave poll results
+    int red_cnt[PEEL_WAVES];
     u64 val;
-    int flag;
 };
 
-// Members of front k - 1 in block w (staged in LDS when STAGED).
+// Members of front kf in block w, from the tagged words (current tags
+// verified by the wait).
+__device__ __forceinline__ u64 tagged_members(const u64 *slot, int w) {
+    const u64 lo = load_relaxed(&slot[2 * w]), hi = load_relaxed(&slot[2 * w + 1]);
+    return (lo & 0xffffffffull) | (hi << 32);
+}
+
+// Waits until every chunk of I has published front kf; stages its members
+// in LDS when STAGED. Returns the front's size, or -1 if the wait gave up.
+// All waves take part.
 template <bool STAGED>
-__device__ __forceinline__ u64 dead_word(const PeelShared &sh, const u64 *alive_p,
-                                         const u64 *alive_k, int w) {
-    if (STAGED) return sh.dead[w];
-    return alive_p[w] & ~alive_k[w];
+__device__ int await_front(const CInst &I, int kf, PeelShared &sh) {
+    const int W = I.W;
+    const int wv = uniform((int)(threadIdx.x >> 6));
+    const u64 *slot = front_slot(I.P.ring, W, kf);
+    const unsigned tag = (unsigned)kf + 1u;
+    for (unsigned polls = 0;; ++polls) {
+        bool bad = false;
+        int cnt = 0;
+        for (int w = threadIdx.x; w < W; w += blockDim.x) {
+            const u64 lo = load_relaxed(&slot[2 * w]), hi = load_relaxed(&slot[2 * w + 1]);
+            bad |= (unsigned)(lo >> 32) != tag || (unsigned)(hi >> 32) != tag;
+            const u64 d = (lo & 0xffffffffull) | (hi << 32);
+            cnt += __popcll(d);
+            if (STAGED) sh.dead[w] = d;
+        }
+        const int wbad = ballot(bad) != 0;
+        const int wcnt = wave_sum(cnt);
+        if (lane_id() == 0) {
+            sh.red_bad[wv] = wbad;
+            sh.red_cnt[wv] = wcnt;
+        }
+        lds_barrier();
+        int anybad = 0, total = 0;
+#pragma unroll
+        for (int v = 0; v < PEEL_WAVES; ++v) {
+            anybad |= sh.red_bad[v];
+            total += sh.red_cnt[v];
+        }
+        anybad = uniform(anybad);
+        total = uniform(total);
+        lds_barrier();  // the next poll (or a chunk) may overwrite the shared words
+        if (!anybad) return total;
+        if (polls == PEEL_POLLS) return -1;
+        __builtin_amdgcn_s_sleep(2);
+    }
 }
 
 // Column cache of an owned chunk c: its matrix words mask[w * Mp + 64c +
@@ -354,35 +396,30 @@ __device__ __forceinline__ void load_column(const CInst &I, int c, u64 (&col)[Q]
     }
 }
 
-// Ranks the points of chunk c that are alive at front k and have no alive
-// dominator; publishes the chunk's result. All waves take part.
-// STAGED: the members of front k - 1 are staged in LDS (W <= PEEL_LDS_ALIVE);
-// a compile-time choice, so that no pointer ever selects between LDS and
-// global memory. Q > 0: the chunk's column is in `col` (load_column; needs
-// STAGED and W <= Q * PEEL_WAVES); Q = 0: the column is streamed, BATCH
-// loads in flight per wave.
+// Ranks the points of owned chunk `own` (chunk c of I) that are alive at
+// front k and have no alive dominator, and publishes them. For k > 0 the
+// members of front k - 1 are those of the last await_front on I (staged in
+// LDS when STAGED, W <= PEEL_LDS_ALIVE; a compile-time choice, so that no
+// pointer ever selects between LDS and global memory). Q > 0: the chunk's
+// column is in `col` (needs STAGED and W <= Q * PEEL_WAVES); Q = 0: it is
+// streamed, BATCH loads in flight per wave. All waves take part.
 template <bool STAGED, int Q, int BATCH>
-__device__ void peel_chunk_impl(CInst &I, int k, int c, PeelShared &sh,
+__device__ void peel_chunk_impl(CInst &I, int k, int c, int own, PeelShared &sh,
                                 const u64 (&col)[Q > 0 ? Q : 1]) {
     const int lane = lane_id();
     const int wv = uniform((int)(threadIdx.x >> 6));
-    const int W = I.W, ns = I.ns;
-    const u64 *alive_k = alive_slot(I.P.alive, W, ns, k);
-    u64 *alive_n = alive_slot(I.P.alive, W, ns, k + 1);
-    const u64 aw = uniform(alive_k[c]);
+    const int W = I.W;
     const int j = c * 64 + lane;
     int *nd = I.P.nd;
-    u64 newly;
+    u64 aw, newly;
     if (k == 0) {
+        const int valid = I.M - c * 64;
+        aw = valid >= 64 ? ~0ull : ((1ull << valid) - 1);
         newly = aw & ballot(nd[j] == 0);
     } else {
-        const u64 *alive_p = alive_slot(I.P.alive, W, ns, k - 1);
+        aw = uniform(sh.own_alive[own]);
         int left = 0;
         if (wv == 0) left = nd[j];  // alive dominators before front k - 1 is removed
-        lds_barrier();  // the previous chunk is done with the shared words
-        if (STAGED && aw != 0)
-            for (int w = threadIdx.x; w < W; w += blockDim.x) sh.dead[w] = alive_p[w] & ~alive_k[w];
-        lds_barrier();
         if (aw != 0) {
             // wave wv takes blocks wv, wv + PEEL_WAVES, ...
             int acc = 0;
@@ -392,13 +429,14 @@ __device__ void peel_chunk_impl(CInst &I, int k, int c, PeelShared &sh,
                 for (int q = 0; q < Q; ++q) acc += __popcll(col[q] & sh.dead[wv + q * PEEL_WAVES]);
             } else {
                 const u64 *__restrict__ src = I.P.mask + (size_t)c * 64 + lane;
+                const u64 *slot = front_slot(I.P.ring, W, k - 1);
                 const size_t Mp = (size_t)I.Mp;
                 for (int w0 = wv; w0 < W; w0 += PEEL_WAVES * BATCH) {
                     u64 x[BATCH], d[BATCH];
 #pragma unroll
                     for (int q = 0; q < BATCH; ++q) {
                         const int w = w0 + q * PEEL_WAVES;
-                        d[q] = w < W ? dead_word<STAGED>(sh, alive_p, alive_k, w) : 0ull;
+                        d[q] = w < W ? (STAGED ? sh.dead[w] : tagged_members(slot, w)) : 0ull;
                         x[q] = d[q] ? src[(size_t)w * Mp] : 0ull;
                     }
 #pragma unroll
@@ -416,43 +454,25 @@ __device__ void peel_chunk_impl(CInst &I, int k, int c, PeelShared &sh,
             if (alive) nd[j] = left;
             newly = aw & ballot(alive && left == 0);
         }
+        lds_barrier();  // the shared partial sums are free again
     }
     if (wv == 0) {
-        const int shard = c % PEEL_SHARDS;
-        u64 *next = peel_slot(I.P.facc, k + 1);
-        // clear this chunk's shard (and, for chunk 0, the total) of front
-        // k + 1's counters: that slot last held front k - 2, whose waits all
-        // ended before front k - 1 could complete; the publish below waits
-        // for these stores, and every front k + 1 publish follows all front k
-        // publishes
-        if (lane == 0) store_relaxed(&next[shard * PEEL_STRIDE], 0ull);
-        if (lane == 0 && c == 0) store_relaxed(&next[PEEL_SHARDS * PEEL_STRIDE], 0ull);
-        store_relaxed(&alive_n[c], aw & ~newly);
-        __builtin_amdgcn_s_waitcnt(0);
-        u64 *slot = peel_slot(I.P.facc, k);
-        if (lane == 0) {
-            const u64 add = ((u64)__popcll(newly) << 32) | 1ull;
-            const u64 old = __hip_atomic_fetch_add(&slot[shard * PEEL_STRIDE], add, __ATOMIC_RELAXED,
-                                                   __HIP_MEMORY_SCOPE_AGENT);
-            // the chunk that completes its shard adds the shard's total to the
-            // front total, the one word that waiters poll
-            const unsigned in_shard = (unsigned)((I.W - shard + PEEL_SHARDS - 1) / PEEL_SHARDS);
-            if ((unsigned)(old & 0xffffffffull) + 1u == in_shard) {
-                const u64 tot = old + add;
-                __hip_atomic_fetch_add(&slot[PEEL_SHARDS * PEEL_STRIDE], (tot & ~0xffffffffull) | 1ull,
-                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            }
+        if (lane < 2) {
+            const u64 tag = (u64)(k + 1) << 32;
+            const u64 half = lane == 0 ? (newly & 0xffffffffull) : (newly >> 32);
+            store_relaxed(&front_slot(I.P.ring, W, k)[2 * c + lane], tag | half);
         }
+        if (lane == 0) sh.own_alive[own] = aw & ~newly;
         if ((newly >> lane) & 1ull) I.rank[j] = k;  // read only by later kernels
     }
 }
 
 // A chunk whose column is streamed.
 template <int BATCH>
-__device__ __forceinline__ void peel_chunk(CInst &I, int k, int c, PeelShared &sh) {
+__device__ __forceinline__ void peel_chunk(CInst &I, int k, int c, int own, PeelShared &sh) {
     const u64 none[1] = {0ull};
-    if (uniform(I.W) <= PEEL_LDS_ALIVE) peel_chunk_impl<true, 0, BATCH>(I, k, c, sh, none);
-    else peel_chunk_impl<false, 0, BATCH>(I, k, c, sh, none);
+    if (uniform(I.W) <= PEEL_LDS_ALIVE) peel_chunk_impl<true, 0, BATCH>(I, k, c, own, sh, none);
+    else peel_chunk_impl<false, 0, BATCH>(I, k, c, own, sh, none);
 }
 
 // Q > 0: the first PEEL_CACHE_SLOTS chunks a workgroup owns keep their
@@ -465,8 +485,6 @@ __global__ __launch_bounds__(64 * PEEL_WAVES) void k_peel(BatchView bv, int nchu
     const int lane = lane_id();
     const int wv = uniform((int)(threadIdx.x >> 6));
     const u64 one = lane == 0 ? 1ull : 0ull;
-    // drop cached lines of alive slots read by an earlier call on these workspaces
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
 
     // front 0: claim and rank chunks until all are claimed. Ticket shard s
     // hands out chunks s, s + TICKET_SHARDS, ...; a workgroup starts at its
@@ -507,7 +525,7 @@ __global__ __launch_bounds__(64 * PEEL_WAVES) void k_peel(BatchView bv, int nchu
         if (t >= (u64)nchunk) break;
         const int b = uniform(find_range(bv.chunk_pref, bv.B, (int)t));
         const int c = (int)t - bv.chunk_pref[b];
-        peel_chunk<BATCH>(bv.tab[b], 0, c, sh);
+        peel_chunk<BATCH>(bv.tab[b], 0, c, nown, sh);
         if (wv == 0) {
             sh.own_b[nown] = b;
             sh.own_c[nown] = c;
@@ -529,40 +547,24 @@ __global__ __launch_bounds__(64 * PEEL_WAVES) void k_peel(BatchView bv, int nchu
 
     for (int k = 1;; ++k) {
         int active = 0;
+        int awaited = -1, size = 0;  // instance whose front k - 1 was last awaited
         for (int q = 0; q < nown; ++q) {
             const int b = uniform(sh.own_b[q]);
             const int c = uniform(sh.own_c[q]);
             const int cum_prev = uniform(sh.own_cum[q]);
             if (cum_prev < 0) continue;  // this instance finished
             CInst &I = bv.tab[b];
-            // wait for front k - 1 of the instance
-            if (wv == 0) {
-                const u64 *total = peel_slot(I.P.facc, k - 1) + PEEL_SHARDS * PEEL_STRIDE;
-                const unsigned shards = (unsigned)(I.W < PEEL_SHARDS ? I.W : PEEL_SHARDS);
-                u64 v = 0;
-                int ok = 1;
-                for (unsigned polls = 0;; ++polls) {
-                    // (points ranked << 32) | shards complete
-                    v = uniform(load_relaxed(total));
-                    if ((unsigned)(v & 0xffffffffull) >= shards) break;
-                    if (polls == (1u << 26)) { ok = 0; break; }
-                    __builtin_amdgcn_s_sleep(2);
-                }
-                sh.val = v;
-                sh.flag = ok;
+            const bool staged = uniform(I.W) <= PEEL_LDS_ALIVE;
+            // wait for front k - 1 of the instance (already staged when the
+            // previous owned chunk belongs to the same instance)
+            if (b != awaited) {
+                size = staged ? await_front<true>(I, k - 1, sh) : await_front<false>(I, k - 1, sh);
+                awaited = b;
             }
-            lds_barrier();
-            const u64 v = uniform(sh.val);
-            const int ok = uniform(sh.flag);
-            // alive slots are reused only after ns fronts: then cached copies of the
-            // slot read ns fronts ago must be dropped before it is read again
-            if (k + 1 >= I.ns) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-            lds_barrier();
-            const int size = (int)(v >> 32);
             const int cum = cum_prev + size;
-            if (!ok || cum >= I.n_stop || size == 0) {
+            if (size <= 0 || cum >= I.n_stop) {
                 if (wv == 0) {
-                    if (!ok || size == 0) atomicOr(&I.P.ctrl->status, ST_INTERNAL);
+                    if (size <= 0) atomicOr(&I.P.ctrl->status, ST_INTERNAL);
                     I.front_info[0] = k - 1;
                     I.front_info[1] = cum_prev;
                     I.front_info[2] = I.n_stop - cum_prev;
@@ -574,11 +576,11 @@ __global__ __launch_bounds__(64 * PEEL_WAVES) void k_peel(BatchView bv, int nchu
             if (wv == 0) sh.own_cum[q] = cum;
             if constexpr (Q > 0) {
                 static_assert(PEEL_CACHE_SLOTS == 2, "one branch per cached slot");
-                if (q == 0) peel_chunk_impl<true, Q, BATCH>(I, k, c, sh, col0);
-                else if (q == 1) peel_chunk_impl<true, Q, BATCH>(I, k, c, sh, col1);
-                else peel_chunk<BATCH>(I, k, c, sh);
+                if (q == 0) peel_chunk_impl<true, Q, BATCH>(I, k, c, q, sh, col0);
+                else if (q == 1) peel_chunk_impl<true, Q, BATCH>(I, k, c, q, sh, col1);
+                else peel_chunk<BATCH>(I, k, c, q, sh);
             } else {
-                peel_chunk<BATCH>(I, k, c, sh);
+                peel_chunk<BATCH>(I, k, c, q, sh);
             }
             active = 1;
         }

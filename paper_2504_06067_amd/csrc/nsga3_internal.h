@@ -58,21 +58,18 @@ struct Ctrl {
     int degen_out;
 };
 
-// front-peeling ring of completion counters: 3 slots of 32 shard counters,
-// each on its own 256-byte line
-constexpr int PEEL_SHARDS = 32;
-constexpr int PEEL_STRIDE = 32;  // u64 words between counters
-constexpr int PEEL_SLOT = (PEEL_SHARDS + 1) * PEEL_STRIDE;
-// words per slot of the alive ring: W rounded up to whole 128-byte lines
-constexpr int alive_slot_words(int W) { return (W + 15) & ~15; }
+// front ring of the peel: PEEL_RING slots, each with two tagged words per
+// chunk, padded to whole 128-byte lines
+constexpr int PEEL_RING = 4;
+constexpr int front_slot_words(int W) { return (2 * W + 15) & ~15; }
 constexpr int PT_ALIGN = 256;    // per-instance point and reference ranges are padded to this
 constexpr int TICKET_SHARDS = 32;   // peel chunk-claim counters of a batch
 constexpr int TICKET_STRIDE = 32;   // u64 words between them (256 bytes)
 
 // Byte offsets of one instance's workspace regions (all 256-byte aligned).
 struct Layout {
-    int M, m, H, N, Mp, W, Hp, ns;
-    size_t ctrl, ft, nd, mask, alive, facc, list, fn, rank, pi, dist, akey, wn,
+    int M, m, H, N, Mp, W, Hp;
+    size_t ctrl, ft, nd, mask, ring, list, fn, rank, pi, dist, akey, wn,
         rho, cnt, off, fill, tpick, members, picked, remain, total;
 };
 
@@ -83,8 +80,7 @@ struct Ptrs {
     float *ft;
     int *nd;
     u64 *mask;
-    u64 *alive;
-    u64 *facc;
+    u64 *ring;          // peel front ring (tagged members per front)
     int *list;
     float *fn;
     int *rank, *pi;
@@ -113,7 +109,7 @@ struct Inst {
     int *degenerate;
     Ptrs P;
     u64 seed;
-    int M, m, H, N, Mp, W, Hp, ns;
+    int M, m, H, N, Mp, W, Hp;
     int n_stop;
     int G;              // dominance: triangle tiles per work item
     int R, nslice;      // association: references per slice, slices
