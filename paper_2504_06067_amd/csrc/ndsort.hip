@@ -325,7 +325,8 @@ struct PeelShared {
     int own_cum[PEEL_OWN_CAP];  // points in the instance's fronts seen so far (-1: done)
     u64 own_alive[PEEL_OWN_CAP];  // its points not yet ranked
     u64 dead[PEEL_LDS_ALIVE];   // members of the awaited front, per block of 64 points
-    int part[PEEL_WAVES][64];   // per-wave partial decrements of the chunk's counts
+    int part[PEEL_CACHE_SLOTS][PEEL_WAVES][64];  // per-wave partial decrements of a chunk's counts
+    int cleft[PEEL_CACHE_SLOTS][64];  // counts of the cached chunks
     int red_bad[PEEL_WAVES];    // per-wave poll results
     int red_cnt[PEEL_WAVES];
     u64 val;
@@ -396,13 +397,28 @@ __device__ __forceinline__ void load_column(const CInst &I, int c, u64 (&col)[Q]
     }
 }
 
+// Publishes the members `newly` of front k in chunk c (one wave; lanes 0 and
+// 1 store the tagged halves) and records the chunk's remaining points.
+__device__ __forceinline__ void publish(CInst &I, int k, int c, int own, u64 aw, u64 newly,
+                                        PeelShared &sh) {
+    const int lane = lane_id();
+    if (lane < 2) {
+        const u64 tag = (u64)(k + 1) << 32;
+        const u64 half = lane == 0 ? (newly & 0xffffffffull) : (newly >> 32);
+        store_relaxed(&front_slot(I.P.ring, I.W, k)[2 * c + lane], tag | half);
+    }
+    if (lane == 0) sh.own_alive[own] = aw & ~newly;
+    if ((newly >> lane) & 1ull) I.rank[c * 64 + lane] = k;  // read only by later kernels
+}
+
 // Ranks the points of owned chunk `own` (chunk c of I) that are alive at
 // front k and have no alive dominator, and publishes them. For k > 0 the
 // members of front k - 1 are those of the last await_front on I (staged in
 // LDS when STAGED, W <= PEEL_LDS_ALIVE; a compile-time choice, so that no
 // pointer ever selects between LDS and global memory). Q > 0: the chunk's
-// column is in `col` (needs STAGED and W <= Q * PEEL_WAVES); Q = 0: it is
-// streamed, BATCH loads in flight per wave. All waves take part.
+// column is in `col` and its counts in sh.cleft[own] (needs STAGED and W <=
+// Q * PEEL_WAVES); Q = 0: its counts are in nd and its column is streamed,
+// BATCH loads in flight per wave. All waves take part.
 template <bool STAGED, int Q, int BATCH>
 __device__ void peel_chunk_impl(CInst &I, int k, int c, int own, PeelShared &sh,
                                 const u64 (&col)[Q > 0 ? Q : 1]) {
@@ -418,8 +434,11 @@ __device__ void peel_chunk_impl(CInst &I, int k, int c, int own, PeelShared &sh,
         newly = aw & ballot(nd[j] == 0);
     } else {
         aw = uniform(sh.own_alive[own]);
-        int left = 0;
-        if (wv == 0) left = nd[j];  // alive dominators before front k - 1 is removed
+        int left = 0;  // alive dominators before front k - 1 is removed
+        if (wv == 0) {
+            if constexpr (Q > 0) left = sh.cleft[own][lane];
+            else left = nd[j];
+        }
         if (aw != 0) {
             // wave wv takes blocks wv, wv + PEEL_WAVES, ...
             int acc = 0;
@@ -443,28 +462,55 @@ __device__ void peel_chunk_impl(CInst &I, int k, int c, int own, PeelShared &sh,
                     for (int q = 0; q < BATCH; ++q) acc += __popcll(x[q] & d[q]);
                 }
             }
-            sh.part[wv][lane] = acc;
+            sh.part[0][wv][lane] = acc;
         }
         lds_barrier();
         newly = 0;
         if (wv == 0 && aw != 0) {
 #pragma unroll
-            for (int v = 0; v < PEEL_WAVES; ++v) left -= sh.part[v][lane];
+            for (int v = 0; v < PEEL_WAVES; ++v) left -= sh.part[0][v][lane];
             const bool alive = (aw >> lane) & 1ull;
-            if (alive) nd[j] = left;
+            if (alive) {
+                if constexpr (Q > 0) sh.cleft[own][lane] = left;
+                else nd[j] = left;
+            }
             newly = aw & ballot(alive && left == 0);
         }
         lds_barrier();  // the shared partial sums are free again
     }
-    if (wv == 0) {
-        if (lane < 2) {
-            const u64 tag = (u64)(k + 1) << 32;
-            const u64 half = lane == 0 ? (newly & 0xffffffffull) : (newly >> 32);
-            store_relaxed(&front_slot(I.P.ring, W, k)[2 * c + lane], tag | half);
-        }
-        if (lane == 0) sh.own_alive[own] = aw & ~newly;
-        if ((newly >> lane) & 1ull) I.rank[j] = k;  // read only by later kernels
+    if (wv == 0) publish(I, k, c, own, aw, newly, sh);
+}
+
+// Both cached chunks (c0, c1: owned slots 0 and 1 of the same instance) in
+// one pass for front k >= 1: every wave sweeps its blocks for both columns,
+// then wave s finishes chunk s.
+template <int Q>
+__device__ void peel_pair(CInst &I, int k, int c0, int c1, PeelShared &sh, const u64 (&col0)[Q],
+                          const u64 (&col1)[Q]) {
+    const int lane = lane_id();
+    const int wv = uniform((int)(threadIdx.x >> 6));
+    int acc0 = 0, acc1 = 0;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const u64 d = sh.dead[wv + q * PEEL_WAVES];
+        acc0 += __popcll(col0[q] & d);
+        acc1 += __popcll(col1[q] & d);
     }
+    sh.part[0][wv][lane] = acc0;
+    sh.part[1][wv][lane] = acc1;
+    lds_barrier();
+    if (wv < 2) {
+        const int s = wv;
+        const u64 aw = uniform(sh.own_alive[s]);
+        int left = sh.cleft[s][lane];
+#pragma unroll
+        for (int v = 0; v < PEEL_WAVES; ++v) left -= sh.part[s][v][lane];
+        const bool alive = (aw >> lane) & 1ull;
+        if (alive) sh.cleft[s][lane] = left;
+        const u64 newly = aw & ballot(alive && left == 0);
+        publish(I, k, s ? c1 : c0, s, aw, newly, sh);
+    }
+    lds_barrier();  // the shared partial sums are free again
 }
 
 // A chunk whose column is streamed.
@@ -527,6 +573,8 @@ __global__ __launch_bounds__(64 * PEEL_WAVES) void k_peel(BatchView bv, int nchu
         const int c = (int)t - bv.chunk_pref[b];
         peel_chunk<BATCH>(bv.tab[b], 0, c, nown, sh);
         if (wv == 0) {
+            // counts of a chunk with a cache slot move to LDS
+            if (Q > 0 && nown < PEEL_CACHE_SLOTS) sh.cleft[nown][lane] = bv.tab[b].P.nd[c * 64 + lane];
             sh.own_b[nown] = b;
             sh.own_c[nown] = c;
             sh.own_cum[nown] = 0;
@@ -576,6 +624,14 @@ __global__ __launch_bounds__(64 * PEEL_WAVES) void k_peel(BatchView bv, int nchu
             if (wv == 0) sh.own_cum[q] = cum;
             if constexpr (Q > 0) {
                 static_assert(PEEL_CACHE_SLOTS == 2, "one branch per cached slot");
+                // both cached chunks of one instance, together
+                if (q == 0 && nown > 1 && uniform(sh.own_b[1]) == b && uniform(sh.own_cum[1]) >= 0) {
+                    if (wv == 0) sh.own_cum[1] = cum;
+                    peel_pair<Q>(I, k, c, uniform(sh.own_c[1]), sh, col0, col1);
+                    active = 1;
+                    q = 1;
+                    continue;
+                }
                 if (q == 0) peel_chunk_impl<true, Q, BATCH>(I, k, c, q, sh, col0);
                 else if (q == 1) peel_chunk_impl<true, Q, BATCH>(I, k, c, q, sh, col1);
                 else peel_chunk<BATCH>(I, k, c, q, sh);
