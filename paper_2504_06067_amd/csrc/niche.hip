@@ -67,9 +67,11 @@ __device__ __forceinline__ long long block_sum_ll(long long v, long long *red) {
     return uniform(s);
 }
 
-// Per-thread cache of the references a plan thread owns (contiguous ranges of
-// up to PLAN_PER references; larger H falls back to global reads).
+// Plan threads own references strided by PLAN_THREADS (thread t: t, t + T,
+// t + 2T, ...; coalesced loads and stores), held in registers PLAN_PER rows
+// at a time; larger H takes several groups of rows.
 constexpr int PLAN_PER = 12;
+constexpr int PLAN_WAVES = PLAN_THREADS / 64;
 
 __device__ __forceinline__ long long block_max_ll(long long v, long long *red) {
 #pragma unroll
@@ -92,64 +94,96 @@ __global__ __launch_bounds__(PLAN_THREADS) void k_niche_plan(BatchView bv) {
     int *off = I.P.off;
     int *tpick = I.P.tpick;
     Ctrl *ctrl = I.P.ctrl;
-    __shared__ long long red[PLAN_THREADS / 64];
+    __shared__ long long red[PLAN_WAVES];
     __shared__ unsigned hist[PLAN_BINS];
-    __shared__ int wtot[PLAN_THREADS / 64];
+    __shared__ int wtot[PLAN_PER * PLAN_WAVES];
     __shared__ u64 cand[64];
     __shared__ u64 cand_thr[1];
     __shared__ int s_sel[4];
+    __shared__ int s_lev[4];  // L*, |T|, P(L*), L* beyond the level window
+    __shared__ int wt2[PLAN_WAVES];
     const int tid = threadIdx.x;
     const int wv = uniform((int)(threadIdx.x >> 6));
     const int lane = lane_id();
     const int K = uniform(I.front_info[2]);
+    // level differences: +1 at rho_j, -1 at rho_j + c_j (levels < PLAN_BINS)
+    int *dlev = (int *)hist;
+    for (int q = tid; q < PLAN_BINS; q += PLAN_THREADS) dlev[q] = 0;
+    if (tid == 0) s_lev[3] = 0;
+    lds_barrier();
 
-    // thread tid owns the contiguous references [b0, b1)
-    const int per = (H + PLAN_THREADS - 1) / PLAN_THREADS;
-    const int b0 = min(tid * per, H), b1 = min(b0 + per, H);
-    const bool cached = per <= PLAN_PER;
+    // rows of PLAN_THREADS references; groups of PLAN_PER rows
+    const int rows = (H + PLAN_THREADS - 1) / PLAN_THREADS;
+    const int groups = (rows + PLAN_PER - 1) / PLAN_PER;
     int rc[PLAN_PER], cc[PLAN_PER];
+    auto load_group = [&](int g) {
 #pragma unroll
-    for (int q = 0; q < PLAN_PER; ++q) {
-        const int j = b0 + q;
-        const bool in = cached && j < b1;
-        rc[q] = in ? rho[j] : 0;
-        cc[q] = in ? cnt[j] : 0;
-    }
-    // Loops over the owned references: compile-time indices into the register
-    // cache when H fits, a plain loop over global memory otherwise.
+        for (int q = 0; q < PLAN_PER; ++q) {
+            const int j = (g * PLAN_PER + q) * PLAN_THREADS + tid;
+            rc[q] = j < H ? rho[j] : 0;
+            cc[q] = j < H ? cnt[j] : 0;
+        }
+    };
+    load_group(0);
+    // Loops over the owned references (group 0 stays loaded when it is the
+    // only one).
 #define PLAN_FOR(BODY)                                                         \
-    if (cached) {                                                              \
+    for (int g = 0; g < groups; ++g) {                                         \
+        if (groups > 1) load_group(g);                                         \
         _Pragma("unroll") for (int q = 0; q < PLAN_PER; ++q) {                 \
-            const int j = b0 + q;                                              \
-            if (j < b1) {                                                      \
+            const int j = (g * PLAN_PER + q) * PLAN_THREADS + tid;             \
+            if (j < H) {                                                       \
                 const int cj = cc[q], rj = rc[q];                              \
                 BODY                                                           \
             }                                                                  \
         }                                                                      \
-    } else {                                                                   \
-        for (int j = b0; j < b1; ++j) {                                        \
-            const int cj = cnt[j], rj = rho[j];                                \
-            BODY                                                               \
-        }                                                                      \
     }
 
-    // exclusive scan of c: per wave, then over the wave totals
-    int local = 0;
-    PLAN_FOR({ (void)rj; local += cj; })
-    const int wincl = wave_incl_scan(local);
-    if (lane == 63) wtot[wv] = wincl;
-    lds_barrier();
-    int run = wincl - local;
-    for (int v = 0; v < wv; ++v) run += wtot[v];
-    lds_barrier();  // wtot is reused below
+    // exclusive scan of c in reference order, group by group: per row a wave
+    // scan; wave 0 scans the (row, wave) totals in order
     long long hi_local = 0;
-    PLAN_FOR({
-        off[j] = run;
-        run += cj;
-        if (cj > 0) hi_local = max(hi_local, (long long)rj + cj);
-    })
-    if (b1 == H && b0 < b1) off[H] = run;
-    const long long total = block_sum_ll((long long)local, red);
+    int carry = 0;
+    for (int g = 0; g < groups; ++g) {
+        if (groups > 1) load_group(g);
+        int incl[PLAN_PER];
+#pragma unroll
+        for (int q = 0; q < PLAN_PER; ++q) {
+            incl[q] = wave_incl_scan(cc[q]);
+            if (lane == 63) wtot[q * PLAN_WAVES + wv] = incl[q];
+            const int j = (g * PLAN_PER + q) * PLAN_THREADS + tid;
+            if (j < H && cc[q] > 0) {
+                if (rc[q] < PLAN_BINS) atomicAdd(&dlev[rc[q]], 1);
+                if (rc[q] + cc[q] < PLAN_BINS) atomicAdd(&dlev[rc[q] + cc[q]], -1);
+            }
+        }
+        lds_barrier();
+        if (wv == 0) {
+            // PLAN_PER * PLAN_WAVES entries in (row, wave) order, three per lane
+            static_assert(PLAN_PER * PLAN_WAVES == 3 * 64, "three totals per lane");
+            const int e0 = 3 * lane;
+            const int t0 = wtot[e0], t1 = wtot[e0 + 1], t2 = wtot[e0 + 2];
+            const int sum = t0 + t1 + t2;
+            const int ex = wave_incl_scan(sum) - sum + carry;
+            wtot[e0] = ex;
+            wtot[e0 + 1] = ex + t0;
+            wtot[e0 + 2] = ex + t0 + t1;
+            if (lane == 63) s_sel[0] = ex + sum;
+        }
+        lds_barrier();
+#pragma unroll
+        for (int q = 0; q < PLAN_PER; ++q) {
+            const int j = (g * PLAN_PER + q) * PLAN_THREADS + tid;
+            if (j < H) {
+                off[j] = wtot[q * PLAN_WAVES + wv] + incl[q] - cc[q];
+                if (cc[q] > 0) hi_local = max(hi_local, (long long)rc[q] + cc[q]);
+            }
+        }
+        carry = uniform(s_sel[0]);
+        lds_barrier();  // wtot and s_sel are reused
+    }
+    if (groups > 1) load_group(0);
+    const long long total = carry;
+    if (tid == 0) off[H] = carry;
 
     if (K >= total) {
         // the whole last front is taken
@@ -163,25 +197,67 @@ __global__ __launch_bounds__(PLAN_THREADS) void k_niche_plan(BatchView bv) {
         }
         return;
     }
-    // L* = max{L : P(L) <= K}; P(0) = 0 <= K < total = P(hi)
-    long long lo = 0, hi = block_max_ll(hi_local, red);
-    while (hi - lo > 1) {
-        const long long mid = (lo + hi) >> 1;
-        long long p = 0;
-        PLAN_FOR({ p += min((long long)cj, max(0ll, mid - rj)); })
-        p = block_sum_ll(p, red);
-        if (p <= K) lo = mid; else hi = mid;
+    // L* = max{L : P(L) <= K}. With a_l = |{j : rho_j <= l < rho_j + c_j}|
+    // (the prefix sum of the level differences), P(L) = a_0 + ... + a_{L-1},
+    // so P(L* + 1) = P(L*) + a_{L*} > K >= P(L*), and a_{L*} = |T|. Thread t
+    // holds levels 4t .. 4t + 3 of the window [0, PLAN_BINS).
+    int Ls, tsize_i;
+    long long pl;
+    {
+        int dv[4], av[4], sd = 0, sa = 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) { dv[q] = dlev[4 * tid + q]; sd += dv[q]; }
+        const int i1 = wave_incl_scan(sd);
+        if (lane == 63) red[wv] = i1;
+        lds_barrier();
+        int run = i1 - sd;
+        for (int v = 0; v < wv; ++v) run += (int)red[v];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) { run += dv[q]; av[q] = run; sa += run; }
+        const int i2 = wave_incl_scan(sa);
+        if (lane == 63) wt2[wv] = i2;
+        lds_barrier();
+        int P = i2 - sa;
+        for (int v = 0; v < wv; ++v) P += wt2[v];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int L = 4 * tid + q;
+            const int Pn = P + av[q];
+            if (P <= K && Pn > K) {
+                s_lev[0] = L;
+                s_lev[1] = av[q];
+                s_lev[2] = P;
+            }
+            if (L == PLAN_BINS - 1 && Pn <= K) s_lev[3] = 1;
+            P = Pn;
+        }
+        lds_barrier();
+        Ls = uniform(s_lev[0]);
+        tsize_i = uniform(s_lev[1]);
+        pl = uniform(s_lev[2]);
     }
-    const int Ls = (int)lo;
-    long long pl = 0;
-    int tcount = 0;
-    PLAN_FOR({
-        pl += min((long long)cj, max(0ll, (long long)Ls - rj));
-        tcount += (cj > 0 && rj <= Ls && Ls < rj + cj);
-    })
-    pl = block_sum_ll(pl, red);
+    if (uniform(s_lev[3])) {
+        // L* lies beyond the window: binary search over P
+        long long lo = PLAN_BINS, hi = block_max_ll(hi_local, red);
+        while (hi - lo > 1) {
+            const long long mid = (lo + hi) >> 1;
+            long long p = 0;
+            PLAN_FOR({ p += min((long long)cj, max(0ll, mid - rj)); })
+            p = block_sum_ll(p, red);
+            if (p <= K) lo = mid; else hi = mid;
+        }
+        Ls = (int)lo;
+        long long p2 = 0;
+        int tcount = 0;
+        PLAN_FOR({
+            p2 += min((long long)cj, max(0ll, (long long)Ls - rj));
+            tcount += (cj > 0 && rj <= Ls && Ls < rj + cj);
+        })
+        pl = block_sum_ll(p2, red);
+        tsize_i = (int)block_sum_ll((long long)tcount, red);
+    }
+    const long long tsize = tsize_i;
     const int r = (int)(K - pl);
-    const long long tsize = block_sum_ll((long long)tcount, red);
 
     // the r least tag-1 keys of T = {j : rho_j <= L* < rho_j + c_j} get one more
     // pick. The r-th least key is found by radix select, 12 bits per pass from
@@ -191,26 +267,27 @@ __global__ __launch_bounds__(PLAN_THREADS) void k_niche_plan(BatchView bv) {
     u64 prefix = 0;
     const bool every = r >= tsize;  // r == |T|: every key of T qualifies
     if (r > 0 && r < tsize) {
+        // keys of the owned members of T (group 0 when it is the only one)
         u64 kc[PLAN_PER];
 #pragma unroll
         for (int q = 0; q < PLAN_PER; ++q) {
-            const int j = b0 + q;
+            const int j = q * PLAN_THREADS + tid;
             kc[q] = 0ull;
-            if (cached && j < b1 && cc[q] > 0 && rc[q] <= Ls && Ls < rc[q] + cc[q])
+            if (groups == 1 && j < H && cc[q] > 0 && rc[q] <= Ls && Ls < rc[q] + cc[q])
                 kc[q] = tie_key(seed, 1u, (unsigned)j, (unsigned)Ls);
         }
-        // calls f(key) for every key of T owned by this thread
+        // calls BODY with `key` for every key of T owned by this thread
 #define PLAN_KEYS(BODY)                                                                       \
-    if (cached) {                                                                             \
+    if (groups == 1) {                                                                        \
         _Pragma("unroll") for (int q = 0; q < PLAN_PER; ++q) {                                \
-            const int j = b0 + q;                                                             \
-            if (j < b1 && cc[q] > 0 && rc[q] <= Ls && Ls < rc[q] + cc[q]) {                   \
+            const int j = q * PLAN_THREADS + tid;                                             \
+            if (j < H && cc[q] > 0 && rc[q] <= Ls && Ls < rc[q] + cc[q]) {                    \
                 const u64 key = kc[q];                                                        \
                 BODY                                                                          \
             }                                                                                 \
         }                                                                                     \
     } else {                                                                                  \
-        for (int j = b0; j < b1; ++j) {                                                       \
+        for (int j = tid; j < H; j += PLAN_THREADS) {                                         \
             if (!(cnt[j] > 0 && rho[j] <= Ls && Ls < rho[j] + cnt[j])) continue;              \
             const u64 key = tie_key(seed, 1u, (unsigned)j, (unsigned)Ls);                     \
             BODY                                                                              \

@@ -241,13 +241,17 @@ __device__ __forceinline__ unsigned wave_max_u32(unsigned v) {
 }
 
 // Inclusive prefix sum over the 64 lanes of a wave.
+// Inclusive scan over the 64 lanes with DPP moves (no LDS round trips):
+// shifts by 1, 2, 4, 8 within each row of 16 lanes, then the last lane of
+// row 0 (2) is added to row 1 (3), then lane 31 to rows 2 and 3. Lanes
+// whose source lies outside the pattern, or whose row is masked off, add 0.
 __device__ __forceinline__ int wave_incl_scan(int v) {
-    const int lane = lane_id();
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        int w = __shfl_up(v, o, 64);
-        if (lane >= o) v += w;
-    }
+    v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, false);  // row_shr:1
+    v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, false);  // row_shr:2
+    v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, false);  // row_shr:4
+    v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, false);  // row_shr:8
+    v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false);  // row_bcast:15, rows 1 and 3
+    v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false);  // row_bcast:31, rows 2 and 3
     return v;
 }
 

@@ -102,3 +102,19 @@ def test_many_levels():
     pi[(rank == 0) & (pi < 8)] = 9  # refs 0..7 have no S members: level-0 picks
     dist = rng.random(M).astype(np.float32)
     check(rank, fi, pi, dist, H, nS + K, 5, dev)
+
+
+@pytest.mark.parametrize("H", [1025, 12288, 12289, 30000])
+def test_reference_rows_and_groups(H):
+    # several rows of plan threads, and more references than one group of rows
+    dev = device()
+    rng = np.random.default_rng(H)
+    M = 3 * H
+    rank = np.where(rng.random(M) < 0.5, 0, 1).astype(np.int32)
+    nS = int((rank == 0).sum())
+    nF = int((rank == 1).sum())
+    K = nF // 3
+    fi = np.array([1, nS, K, 2], np.int32)
+    pi = rng.integers(0, H, M).astype(np.int32)
+    dist = rng.random(M).astype(np.float32)
+    check(rank, fi, pi, dist, H, nS + K, 11 + H, dev)
