@@ -46,6 +46,7 @@ Layout make_layout(int M, int m, int H, int N) {
     L.tpick = take(Hp * 4);
     L.members = take(Mp * 4);
     L.picked = take(Mp * 4);
+    L.tcnt = take((Mp + COMPACT_TILE - 1) / COMPACT_TILE * 4);
     L.remain = take((W + (size_t)H + 2) * 8);
     L.total = o;
     return L;
@@ -73,6 +74,7 @@ Ptrs carve(const Layout &L, void *ws) {
     P.tpick = (int *)(b + L.tpick);
     P.members = (int *)(b + L.members);
     P.picked = (int *)(b + L.picked);
+    P.tcnt = (int *)(b + L.tcnt);
     P.remain = (u64 *)(b + L.remain);
     return P;
 }

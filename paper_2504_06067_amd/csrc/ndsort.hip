@@ -75,7 +75,10 @@ __global__ __launch_bounds__(256) void k_prep(BatchView bv, int npt) {
                 }
             }
         }
-        if (j < M && (bv.run & RUN_NICHE)) I.P.picked[j] = 0;
+        if (j < M && (bv.run & RUN_NICHE)) {
+            I.P.picked[j] = 0;
+            if (j % COMPACT_TILE == 0) I.P.tcnt[j / COMPACT_TILE] = 0;
+        }
         if (ballot(bad) != 0 && lane_id() == 0) atomicOr(&I.P.ctrl->status, ST_NONFINITE);
     } else {
         const int base = uniform((int)(blockIdx.x * blockDim.x)) - npt;

@@ -381,12 +381,16 @@ __global__ __launch_bounds__(PLAN_THREADS) void k_niche_plan(BatchView bv) {
     }
 }
 
+// Also counts the members of S per compaction tile (one atomic per wave).
 __global__ __launch_bounds__(256) void k_niche_scatter(BatchView bv) {
     const Local L = locate(bv.pt_pref, bv.B);
     CInst &I = bv.tab[L.b];
     const int x = L.i;
-    if (x >= I.M) return;
-    if (I.rank[x] != I.front_info[0]) return;
+    const int l = I.front_info[0];
+    const int rk = x < I.M ? I.rank[x] : -1;
+    const u64 in_s = ballot(rk >= 0 && rk < l);
+    if (lane_id() == 0 && in_s != 0) atomicAdd(&I.P.tcnt[x / COMPACT_TILE], __popcll(in_s));
+    if (rk != l) return;
     const int p = I.pi[x];
     if (p < 0 || p >= I.H) return;
     const int slot = atomicAdd(&I.P.fill[p], 1);
@@ -466,6 +470,7 @@ __global__ __launch_bounds__(256) void k_niche_pick(BatchView bv) {
     int *members = I.P.members;
     u64 *remain_g = I.P.remain;
     int *picked = I.P.picked;
+    int *tcnt = I.P.tcnt;
     const int wv = threadIdx.x >> 6;
     const int lane = lane_id();
     const int j = base - bv.ref_pref[b] + wv;
@@ -475,7 +480,11 @@ __global__ __launch_bounds__(256) void k_niche_pick(BatchView bv) {
     const int c = cnt[j];
     int *seg = members + off[j];
     if (t >= c) {
-        for (int i = lane; i < c; i += 64) picked[seg[i]] = 1;
+        for (int i = lane; i < c; i += 64) {
+            const int x = seg[i];
+            picked[x] = 1;
+            atomicAdd(&tcnt[x / COMPACT_TILE], 1);
+        }
         return;
     }
     const int rj = rho[j];
@@ -488,7 +497,11 @@ __global__ __launch_bounds__(256) void k_niche_pick(BatchView bv) {
             best = k < best ? k : best;
         }
         best = wave_min_u64(best);
-        if (lane == 0) picked[(int)(unsigned)(best & 0xffffffffull)] = 1;
+        if (lane == 0) {
+            const int x = (int)(unsigned)(best & 0xffffffffull);
+            picked[x] = 1;
+            atomicAdd(&tcnt[x / COMPACT_TILE], 1);
+        }
         return;
     }
     int *buf;
@@ -548,68 +561,55 @@ __global__ __launch_bounds__(256) void k_niche_pick(BatchView bv) {
         // remove position pos
         if (lane == 0) rem[pos >> 6] &= ~(1ull << (pos & 63));
         if (lane == (pos >> 6) / s) own -= 1;
-        if (lane == 0) picked[buf[pos]] = 1;
+        if (lane == 0) {
+            const int x = buf[pos];
+            picked[x] = 1;
+            atomicAdd(&tcnt[x / COMPACT_TILE], 1);
+        }
         wave_sync();
     }
 }
 
-// Compaction of {x : rank[x] < l or picked[x]} in ascending order: one
-// workgroup per instance sweeps its points COMPACT_SPAN at a time. Wave w of
-// a sweep owns COMPACT_ROUNDS consecutive groups of 64 points; lane L reads
-// point 64 q + L of group q (coalesced), a ballot per group gives the flags,
-// and popcounts of the ballots give every point's output position.
-constexpr int COMPACT_THREADS = 1024;
-constexpr int COMPACT_ROUNDS = 16;
-constexpr int COMPACT_WAVES = COMPACT_THREADS / 64;
-constexpr int COMPACT_SPAN = COMPACT_THREADS * COMPACT_ROUNDS;
-
-__global__ __launch_bounds__(COMPACT_THREADS) void k_compact(BatchView bv) {
-    __shared__ int wsum[COMPACT_WAVES];
-    CInst &I = bv.tab[blockIdx.x];
-    const int l = I.front_info[0];
-    const int M = I.M, N = I.N;
+// Compaction of {x : rank[x] < l or picked[x]} in ascending order, one
+// workgroup per tile of COMPACT_TILE points. The scatter and pick kernels
+// counted the selected points of every tile, so a tile's first output
+// position is the sum of the counts before it (one wave adds them up); a
+// ballot per wave and the wave counts give every point's position.
+// Grid: all instances' padded point ranges.
+static_assert(COMPACT_TILE == PT_ALIGN, "a workgroup of the point grid is one tile");
+__global__ __launch_bounds__(COMPACT_TILE) void k_compact(BatchView bv) {
+    __shared__ int s_base;
+    __shared__ int wcnt[COMPACT_TILE / 64];
+    const Local L = locate(bv.pt_pref, bv.B);
+    CInst &I = bv.tab[L.b];
+    const int x = L.i;
+    const int M = I.M, N = I.N, l = I.front_info[0];
+    const int t = uniform(x / COMPACT_TILE);
+    if (t * COMPACT_TILE >= M) return;  // a tile of padding only
     const int wv = threadIdx.x >> 6;
     const int lane = lane_id();
-    int carry = 0;
-    for (int base = 0; base < M; base += COMPACT_SPAN) {
-        const int x0 = base + wv * 64 * COMPACT_ROUNDS + lane;
-        // all loads first, so that they are in flight together
-        int rk[COMPACT_ROUNDS], pk[COMPACT_ROUNDS];
-#pragma unroll
-        for (int q = 0; q < COMPACT_ROUNDS; ++q) {
-            const int x = x0 + 64 * q;
-            rk[q] = x < M ? I.rank[x] : -1;
-            pk[q] = x < M ? I.P.picked[x] : 0;
-        }
-        u64 fl[COMPACT_ROUNDS];
-        int n = 0;
-#pragma unroll
-        for (int q = 0; q < COMPACT_ROUNDS; ++q) {
-            fl[q] = ballot((rk[q] >= 0 && rk[q] < l) || pk[q] != 0);
-            n += __popcll(fl[q]);
-        }
-        if (lane == 0) wsum[wv] = n;
-        lds_barrier();
-        int woff = 0, total = 0;
-#pragma unroll
-        for (int v = 0; v < COMPACT_WAVES; ++v) {
-            const int t = wsum[v];
-            woff += v < wv ? t : 0;
-            total += t;
-        }
-        int pos = carry + woff;
-#pragma unroll
-        for (int q = 0; q < COMPACT_ROUNDS; ++q) {
-            if ((fl[q] >> lane) & 1ull) {
-                const int p = pos + mbcnt(fl[q]);
-                if (p < N) I.selected[p] = x0 + 64 * q;
-            }
-            pos += __popcll(fl[q]);
-        }
-        carry += uniform(total);
-        lds_barrier();  // wsum is reused
+    const int *tcnt = I.P.tcnt;
+    if (wv == 0) {
+        int sum = 0;
+        for (int u = lane; u < t; u += 64) sum += tcnt[u];
+        sum = wave_sum(sum);
+        if (lane == 0) s_base = sum;
     }
-    if (threadIdx.x == 0 && carry != N) atomicOr(&I.P.ctrl->status, ST_INTERNAL);
+    const int rk = x < M ? I.rank[x] : -1;
+    const bool sel = x < M && ((rk >= 0 && rk < l) || I.P.picked[x] != 0);
+    const u64 fl = ballot(sel);
+    if (lane == 0) wcnt[wv] = __popcll(fl);
+    lds_barrier();
+    int pos = s_base;
+    for (int v = 0; v < wv; ++v) pos += wcnt[v];
+    pos += mbcnt(fl);
+    if (sel && pos < N) I.selected[pos] = x;
+    // the last tile checks the total against N
+    if (threadIdx.x == 0 && (t + 1) * COMPACT_TILE >= M) {
+        int total = s_base;
+        for (int v = 0; v < COMPACT_TILE / 64; ++v) total += wcnt[v];
+        if (total != N) atomicOr(&I.P.ctrl->status, ST_INTERNAL);
+    }
 }
 
 hipError_t launch_niche(const HostPlan &hp, const BatchView &bv, hipStream_t s) {
@@ -619,7 +619,7 @@ hipError_t launch_niche(const HostPlan &hp, const BatchView &bv, hipStream_t s) 
     NSGA3_LAUNCH("niche_plan", k_niche_plan, dim3(hp.B), dim3(PLAN_THREADS), 0, s, bv);
     NSGA3_LAUNCH("niche_scatter", k_niche_scatter, dim3(pblocks), dim3(256), 0, s, bv);
     NSGA3_LAUNCH("niche_pick", k_niche_pick, dim3((unsigned)(hp.nref / 4)), dim3(256), 0, s, bv);
-    NSGA3_LAUNCH("compact", k_compact, dim3(hp.B), dim3(COMPACT_THREADS), 0, s, bv);
+    NSGA3_LAUNCH("compact", k_compact, dim3(hp.npt / 256), dim3(COMPACT_TILE), 0, s, bv);
     return hipGetLastError();
 }
 

@@ -63,6 +63,7 @@ struct Ctrl {
 constexpr int PEEL_RING = 4;
 constexpr int front_slot_words(int W) { return (2 * W + 15) & ~15; }
 constexpr int PT_ALIGN = 256;    // per-instance point and reference ranges are padded to this
+constexpr int COMPACT_TILE = 256;  // points per compaction tile (one workgroup)
 constexpr int TICKET_SHARDS = 32;   // peel chunk-claim counters of a batch
 constexpr int TICKET_STRIDE = 32;   // u64 words between them (256 bytes)
 
@@ -70,7 +71,7 @@ constexpr int TICKET_STRIDE = 32;   // u64 words between them (256 bytes)
 struct Layout {
     int M, m, H, N, Mp, W, Hp;
     size_t ctrl, ft, nd, mask, ring, list, fn, rank, pi, dist, akey, wn,
-        rho, cnt, off, fill, tpick, members, picked, remain, total;
+        rho, cnt, off, fill, tpick, members, picked, tcnt, remain, total;
 };
 
 Layout make_layout(int M, int m, int H, int N);
@@ -88,6 +89,7 @@ struct Ptrs {
     u64 *akey;
     float *wn;
     int *rho, *cnt, *off, *fill, *tpick, *members, *picked;
+    int *tcnt;          // selected points per compaction tile
     u64 *remain;
 };
 
