@@ -167,6 +167,16 @@ __global__ __launch_bounds__(256) void k_blob(Blob b, unsigned *dst, int n) {
     for (int i = threadIdx.x; i < n; i += 256) dst[i] = b.w[i];
 }
 
+// The whole header of a one-instance call, and the start of that instance
+// (as k_init), in one launch.
+__global__ __launch_bounds__(256) void k_blob_init(Blob b, unsigned *dst, int n, Ctrl *ctrl,
+                                                   int *front_info, int n_stop, int run,
+                                                   u64 *ticket) {
+    for (int i = threadIdx.x; i < n; i += 256) dst[i] = b.w[i];
+    init_instance(ctrl, front_info, n_stop, run, threadIdx.x);
+    if (threadIdx.x < TICKET_SHARDS) ticket[threadIdx.x * TICKET_STRIDE] = 0;
+}
+
 // A planned call: per-instance regions, the header bytes, the host plan and
 // the device view.
 struct Plan {
@@ -311,8 +321,21 @@ hipError_t upload(const void *src_, size_t bytes, void *dst_, hipStream_t s) {
 
 // Enqueues the header copy, then the stages of `run`.
 static hipError_t enqueue(Plan &p, char *ws, hipStream_t s) {
-    hipError_t e = upload(p.hdr.data(), p.hdr.size(), ws + p.inst_total, s);
-    if (e == hipSuccess) e = launch_prepare(p.hp, p.bv, s);
+    hipError_t e;
+    const bool fused = p.hp.B == 1 && p.hdr.size() <= sizeof(Blob);
+    if (fused) {
+        Blob blob;
+        memcpy(blob.w, p.hdr.data(), p.hdr.size());
+        Inst I0;
+        memcpy(&I0, p.hdr.data() + p.hl.tab, sizeof(Inst));
+        NSGA3_LAUNCH("header", k_blob_init, dim3(1), dim3(256), 0, s, blob,
+                     (unsigned *)(ws + p.inst_total), (int)(p.hdr.size() / 4), I0.P.ctrl,
+                     I0.front_info, I0.n_stop, p.bv.run, p.bv.ticket);
+        e = hipGetLastError();
+    } else {
+        e = upload(p.hdr.data(), p.hdr.size(), ws + p.inst_total, s);
+    }
+    if (e == hipSuccess) e = launch_prepare(p.hp, p.bv, fused, s);
     const int run = p.bv.run;
     if (e == hipSuccess && (run & RUN_ND)) e = launch_nd_sort(p.hp, p.bv, s);
     if (e == hipSuccess && (run & RUN_NORM)) e = launch_normalize(p.hp, p.bv, s);

@@ -24,25 +24,8 @@ long long dominance_tiles(int W) { return (long long)W * (W + 1) / 2; }
 
 __global__ __launch_bounds__(256) void k_init(BatchView bv) {
     CInst &I = bv.tab[blockIdx.x];
-    Ctrl *ctrl = I.P.ctrl;
-    const int t = threadIdx.x;
-    if (t == 0) {
-        ctrl->status = 0;
-        ctrl->list_count = 0;
-        if (bv.run & RUN_ND) {
-            // a defined value even if the peel stops on an internal error
-            I.front_info[0] = 0;
-            I.front_info[1] = 0;
-            I.front_info[2] = I.n_stop;
-            I.front_info[3] = 0;
-        }
-    }
-    if (blockIdx.x == 0 && t < TICKET_SHARDS) bv.ticket[t * TICKET_STRIDE] = 0;
-    if (t < NSGA3_MAX_OBJECTIVES) {
-        ctrl->zmin_enc[t] = 0xffffffffu;
-        ctrl->fmax_enc[t] = 0u;
-        ctrl->ext_key[t] = ~0ull;
-    }
+    init_instance(I.P.ctrl, I.front_info, I.n_stop, bv.run, threadIdx.x);
+    if (blockIdx.x == 0 && threadIdx.x < TICKET_SHARDS) bv.ticket[threadIdx.x * TICKET_STRIDE] = 0;
 }
 
 // Grid: [all instances' padded points][all instances' padded references].
@@ -648,8 +631,8 @@ __global__ __launch_bounds__(64 * PEEL_WAVES) void k_peel(BatchView bv, int nchu
     }
 }
 
-hipError_t launch_prepare(const HostPlan &hp, const BatchView &bv, hipStream_t s) {
-    NSGA3_LAUNCH("init", k_init, dim3(hp.B), dim3(256), 0, s, bv);
+hipError_t launch_prepare(const HostPlan &hp, const BatchView &bv, bool init_done, hipStream_t s) {
+    if (!init_done) NSGA3_LAUNCH("init", k_init, dim3(hp.B), dim3(256), 0, s, bv);
     NSGA3_LAUNCH("prep", k_prep, dim3((hp.npt + hp.nref) / 256), dim3(256), 0, s, bv, hp.npt);
     return hipGetLastError();
 }

@@ -9,9 +9,10 @@
 //   k_norm_reduce   per-objective min (ideal) and max over S_t; builds the
 //                   S_t index list (order irrelevant to every result); in a
 //                   whole selection also prepares the association outputs
-//   k_norm_extreme  per-axis ASF argmin over S_t as a 64-bit (value, index) min
-//   k_norm_solve    one wave per instance (one launch per m): FP64
-//                   elimination, degeneracy tests
+//   k_norm_extreme  per-axis ASF argmin over S_t as a 64-bit (value, index) min;
+//                   the last block of an instance then solves for the
+//                   intercepts with one wave (FP64 elimination, degeneracy
+//                   tests)
 //   k_norm_apply    Fn = (f - z) * (1 / a) over S_t (stage call; a whole
 //                   selection forms Fn in the association sweep)
 #include "nsga3_internal.h"
@@ -67,47 +68,6 @@ __global__ __launch_bounds__(256) void k_norm_reduce(BatchView bv) {
     if (in) I.P.list[off + mbcnt(bal)] = x;
 }
 
-// ASF_k(x) = max(f'_k, max_{j != k} 1e6 * f'_j) with f' = f - z >= 0 on S_t,
-// so the raw float bits order like the values; ties go to the least index.
-// Grid: padded points of the group's instances (one launch per m).
-template <int MO>
-__global__ __launch_bounds__(256) void k_norm_extreme(BatchView bv, int gs, int gn, int pt0) {
-    const int base = uniform(pt0 + (int)(blockIdx.x * blockDim.x));
-    const int gi = uniform(find_range(bv.pt_pref, bv.B, base));
-    CInst &I = bv.tab[gi];
-    Ctrl *ctrl = I.P.ctrl;
-    const int n = ctrl->list_count;
-    const int i = base - bv.pt_pref[gi] + (int)threadIdx.x;
-    if (base - bv.pt_pref[gi] >= n || I.m != MO) return;
-    const bool in = i < n;
-    const int x = in ? I.P.list[i] : 0;
-    float fp[MO], g[MO];
-#pragma unroll
-    for (int k = 0; k < MO; ++k) {
-        const float z = ord2f(ctrl->zmin_enc[k]);
-        fp[k] = in ? I.F[(size_t)x * MO + k] - z : 0.0f;
-        g[k] = 1e6f * fp[k];
-    }
-    // largest and second largest of g, with the position of the largest
-    float g1 = g[0], g2 = -INFINITY;
-    int p1 = 0;
-#pragma unroll
-    for (int k = 1; k < MO; ++k) {
-        if (g[k] > g1) { g2 = g1; g1 = g[k]; p1 = k; }
-        else if (g[k] > g2) g2 = g[k];
-    }
-#pragma unroll
-    for (int k = 0; k < MO; ++k) {
-        const float other = (k == p1) ? g2 : g1;
-        const float asf = fmaxf(fp[k], other);
-        u64 key = in ? (((u64)__float_as_uint(asf) << 32) | (unsigned)x) : ~0ull;
-        key = wave_min_u64(key);
-        if (lane_id() == 0 && key != ~0ull) atomicMin(&ctrl->ext_key[k], key);
-    }
-    (void)gs;
-    (void)gn;
-}
-
 // Doubles move between lanes as two 32-bit halves.
 __device__ __forceinline__ double read_lane_f64(double v, int L) {
     const u64 u = (u64)__double_as_longlong(v);
@@ -122,15 +82,14 @@ __device__ __forceinline__ double shfl_f64(double v, int src) {
     return __longlong_as_double((long long)(((u64)hi << 32) | lo));
 }
 
-// One wave per instance of the m-group order[gs .. gs + gn). E[k][j] =
+// One wave per instance. E[k][j] =
 // f(e_k)_j - z_j in FP64; E b = 1 is solved by Gaussian elimination with
 // partial pivoting (largest |pivot|, least row on ties), the rows spread over
 // the lanes (lane i holds the row at position i; a swap exchanges two lanes'
 // rows), every product and difference rounded separately; a_k = 1 / b_k
 // unless degenerate.
 template <int MO>
-__global__ __launch_bounds__(64) void k_norm_solve(BatchView bv, int gs) {
-    CInst &I = bv.tab[bv.order[gs + blockIdx.x]];
+__device__ void norm_solve(CInst &I) {
     Ctrl *ctrl = I.P.ctrl;
     const int lane = lane_id();
     const int M = I.M;
@@ -224,6 +183,65 @@ __global__ __launch_bounds__(64) void k_norm_solve(BatchView bv, int gs) {
     if (lane == 0) *I.degenerate = degen;
 }
 
+// ASF_k(x) = max(f'_k, max_{j != k} 1e6 * f'_j) with f' = f - z >= 0 on S_t,
+// so the raw float bits order like the values; ties go to the least index.
+// The last of an instance's blocks to finish (a counter in its control block)
+// then solves for the intercepts with one wave. Grid: padded points of the
+// group's instances (one launch per m).
+template <int MO>
+__global__ __launch_bounds__(256) void k_norm_extreme(BatchView bv, int gs, int gn, int pt0) {
+    const int base = uniform(pt0 + (int)(blockIdx.x * blockDim.x));
+    const int gi = uniform(find_range(bv.pt_pref, bv.B, base));
+    CInst &I = bv.tab[gi];
+    Ctrl *ctrl = I.P.ctrl;
+    const int n = ctrl->list_count;
+    const int i = base - bv.pt_pref[gi] + (int)threadIdx.x;
+    // blocks 0 .. nblk - 1 of the instance take part (block 0 also when S_t is empty)
+    const int nblk = n > 0 ? (n + 255) / 256 : 1;
+    if (base - bv.pt_pref[gi] >= nblk * 256 || I.m != MO) return;
+    const bool in = i < n;
+    const int x = in ? I.P.list[i] : 0;
+    float fp[MO], g[MO];
+#pragma unroll
+    for (int k = 0; k < MO; ++k) {
+        const float z = ord2f(ctrl->zmin_enc[k]);
+        fp[k] = in ? I.F[(size_t)x * MO + k] - z : 0.0f;
+        g[k] = 1e6f * fp[k];
+    }
+    // largest and second largest of g, with the position of the largest
+    float g1 = g[0], g2 = -INFINITY;
+    int p1 = 0;
+#pragma unroll
+    for (int k = 1; k < MO; ++k) {
+        if (g[k] > g1) { g2 = g1; g1 = g[k]; p1 = k; }
+        else if (g[k] > g2) g2 = g[k];
+    }
+#pragma unroll
+    for (int k = 0; k < MO; ++k) {
+        const float other = (k == p1) ? g2 : g1;
+        const float asf = fmaxf(fp[k], other);
+        u64 key = in ? (((u64)__float_as_uint(asf) << 32) | (unsigned)x) : ~0ull;
+        key = wave_min_u64(key);
+        if (lane_id() == 0 && key != ~0ull) atomicMin(&ctrl->ext_key[k], key);
+    }
+    (void)gs;
+    (void)gn;
+    __shared__ int s_last;
+    lds_barrier();  // every wave's minima are issued
+    if (threadIdx.x == 0) {
+        // release: this block's minima are performed before the count; the
+        // last block acquires them all
+        const int done = __hip_atomic_fetch_add(&ctrl->ext_done, 1, __ATOMIC_ACQ_REL,
+                                                __HIP_MEMORY_SCOPE_AGENT);
+        s_last = done == nblk - 1;
+    }
+    lds_barrier();
+    if (s_last && threadIdx.x < 64) {
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        norm_solve<MO>(I);
+    }
+}
+
 __global__ __launch_bounds__(256) void k_norm_apply(BatchView bv) {
     const Local L = locate(bv.pt_pref, bv.B);
     CInst &I = bv.tab[L.b];
@@ -252,22 +270,6 @@ hipError_t launch_normalize(const HostPlan &hp, const BatchView &bv, hipStream_t
             default: return hipErrorInvalidValue;
         }
 #undef NSGA3_EXT_CASE
-    }
-    for (int g = 0; g < hp.ngroups; ++g) {
-        const unsigned gn = (unsigned)(hp.grp_start[g + 1] - hp.grp_start[g]);
-#define NSGA3_SOLVE_CASE(MO)                                                                   \
-    case MO:                                                                                   \
-        NSGA3_LAUNCH("norm_solve", k_norm_solve<MO>, dim3(gn), dim3(64), 0, s, bv,             \
-                     hp.grp_start[g]);                                                         \
-        break;
-        switch (hp.grp_m[g]) {
-            NSGA3_SOLVE_CASE(2) NSGA3_SOLVE_CASE(3) NSGA3_SOLVE_CASE(4) NSGA3_SOLVE_CASE(5)
-            NSGA3_SOLVE_CASE(6) NSGA3_SOLVE_CASE(7) NSGA3_SOLVE_CASE(8) NSGA3_SOLVE_CASE(9)
-            NSGA3_SOLVE_CASE(10) NSGA3_SOLVE_CASE(11) NSGA3_SOLVE_CASE(12) NSGA3_SOLVE_CASE(13)
-            NSGA3_SOLVE_CASE(14) NSGA3_SOLVE_CASE(15) NSGA3_SOLVE_CASE(16)
-            default: return hipErrorInvalidValue;
-        }
-#undef NSGA3_SOLVE_CASE
     }
     // a whole selection forms Fn inside the association sweep instead
     if (!(bv.run & RUN_ASSOC))

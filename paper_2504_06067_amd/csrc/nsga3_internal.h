@@ -56,6 +56,7 @@ struct Ctrl {
     double icpt_out[NSGA3_MAX_OBJECTIVES];
     int ext_out[NSGA3_MAX_OBJECTIVES];
     int degen_out;
+    int ext_done;            // blocks of the extreme search that finished
 };
 
 // front ring of the peel: PEEL_RING slots, each with two tagged words per
@@ -302,6 +303,29 @@ struct ProfScope {
         hipLaunchKernelGGL(__VA_ARGS__);     \
     } while (0)
 
+// Per-instance start of a call (one workgroup, thread t): status, list
+// counter, front fill default, normalization accumulators.
+__device__ __forceinline__ void init_instance(Ctrl *ctrl, int *front_info, int n_stop, int run,
+                                              int t) {
+    if (t == 0) {
+        ctrl->status = 0;
+        ctrl->list_count = 0;
+        ctrl->ext_done = 0;
+        if (run & RUN_ND) {
+            // a defined value even if the peel stops on an internal error
+            front_info[0] = 0;
+            front_info[1] = 0;
+            front_info[2] = n_stop;
+            front_info[3] = 0;
+        }
+    }
+    if (t < NSGA3_MAX_OBJECTIVES) {
+        ctrl->zmin_enc[t] = 0xffffffffu;
+        ctrl->fmax_enc[t] = 0u;
+        ctrl->ext_key[t] = ~0ull;
+    }
+}
+
 // -------------------------------------------------------------- launchers
 
 struct Dev {
@@ -330,7 +354,8 @@ hipError_t upload(const void *src, size_t bytes, void *dst, hipStream_t s);
 size_t evolve_header_bytes(int B);
 hipError_t launch_evolve(const nsga3_evolve_slot *slots, int B, char *ws, hipStream_t s);
 
-hipError_t launch_prepare(const HostPlan &hp, const BatchView &bv, hipStream_t s);
+// init_done: the instance was initialized with the header copy (k_blob_init).
+hipError_t launch_prepare(const HostPlan &hp, const BatchView &bv, bool init_done, hipStream_t s);
 hipError_t launch_nd_sort(const HostPlan &hp, const BatchView &bv, hipStream_t s);
 hipError_t launch_normalize(const HostPlan &hp, const BatchView &bv, hipStream_t s);
 hipError_t launch_associate(const HostPlan &hp, const BatchView &bv, hipStream_t s);
