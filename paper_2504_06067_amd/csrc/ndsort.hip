@@ -127,9 +127,11 @@ __device__ __forceinline__ int row_of(long long t) {
 }
 
 // GW consecutive column values of one objective (one scalar load). The
-// group width keeps GW * m values within the scalar register budget.
+// group width keeps GW * m values within the scalar register budget (no
+// spills, 8 waves per SIMD): the wider the group, the fewer scalar loads per
+// column point, which matter most for large m.
 template <int MO>
-constexpr int col_group() { return MO <= 4 ? 8 : (MO <= 8 ? 4 : 2); }
+constexpr int col_group() { return MO <= 6 ? 8 : (MO <= 13 ? 4 : 2); }
 
 template <int GW>
 struct alignas(4 * GW) ColV {
