@@ -299,7 +299,7 @@ constexpr int PEEL_OWN_CAP = 1024;
 constexpr int PEEL_LDS_ALIVE = 2048;  // blocks whose members are staged in LDS (M <= 131072)
 constexpr int PEEL_BATCH = 16;        // matrix loads in flight per wave (streamed columns)
 constexpr int PEEL_CACHE_SLOTS = 2;   // owned chunks whose columns stay in registers
-constexpr unsigned PEEL_POLLS = 1u << 24;  // polls before a wait gives up (an internal error)
+constexpr unsigned PEEL_POLLS = 1u << 22;  // polls of one word before a wait gives up (an internal error)
 
 // Tagged members of front k: slot k % PEEL_RING of the ring (2W words,
 // padded to whole 128-byte lines).
@@ -328,44 +328,50 @@ __device__ __forceinline__ u64 tagged_members(const u64 *slot, int w) {
 }
 
 // Waits until every chunk of I has published front kf; stages its members
-// in LDS when STAGED. Returns the front's size, or -1 if the wait gave up.
-// All waves take part.
+// in LDS when STAGED. Returns the front's size, or -1 if a wait gave up.
+// Every thread polls its own words until their tags are current, so the
+// workgroup meets once, when all are. All waves take part.
 template <bool STAGED>
 __device__ int await_front(const CInst &I, int kf, PeelShared &sh) {
     const int W = I.W;
     const int wv = uniform((int)(threadIdx.x >> 6));
     const u64 *slot = front_slot(I.P.ring, W, kf);
     const unsigned tag = (unsigned)kf + 1u;
-    for (unsigned polls = 0;; ++polls) {
-        bool bad = false;
-        int cnt = 0;
-        for (int w = threadIdx.x; w < W; w += blockDim.x) {
-            const u64 lo = load_relaxed(&slot[2 * w]), hi = load_relaxed(&slot[2 * w + 1]);
-            bad |= (unsigned)(lo >> 32) != tag || (unsigned)(hi >> 32) != tag;
-            const u64 d = (lo & 0xffffffffull) | (hi << 32);
-            cnt += __popcll(d);
-            if (STAGED) sh.dead[w] = d;
+    bool bad = false;
+    int cnt = 0;
+    for (int w = threadIdx.x; w < W; w += blockDim.x) {
+        u64 lo, hi;
+        for (unsigned polls = 0;; ++polls) {
+            lo = load_relaxed(&slot[2 * w]);
+            hi = load_relaxed(&slot[2 * w + 1]);
+            if ((unsigned)(lo >> 32) == tag && (unsigned)(hi >> 32) == tag) break;
+            if (polls == PEEL_POLLS) {
+                bad = true;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
         }
-        const int wbad = ballot(bad) != 0;
-        const int wcnt = wave_sum(cnt);
-        if (lane_id() == 0) {
-            sh.red_bad[wv] = wbad;
-            sh.red_cnt[wv] = wcnt;
-        }
-        lds_barrier();
-        int anybad = 0, total = 0;
-#pragma unroll
-        for (int v = 0; v < PEEL_WAVES; ++v) {
-            anybad |= sh.red_bad[v];
-            total += sh.red_cnt[v];
-        }
-        anybad = uniform(anybad);
-        total = uniform(total);
-        lds_barrier();  // the next poll (or a chunk) may overwrite the shared words
-        if (!anybad) return total;
-        if (polls == PEEL_POLLS) return -1;
-        __builtin_amdgcn_s_sleep(2);
+        const u64 d = (lo & 0xffffffffull) | (hi << 32);
+        cnt += __popcll(d);
+        if (STAGED) sh.dead[w] = d;
     }
+    const int wbad = ballot(bad) != 0;
+    const int wcnt = wave_sum(cnt);
+    if (lane_id() == 0) {
+        sh.red_bad[wv] = wbad;
+        sh.red_cnt[wv] = wcnt;
+    }
+    lds_barrier();
+    int anybad = 0, total = 0;
+#pragma unroll
+    for (int v = 0; v < PEEL_WAVES; ++v) {
+        anybad |= sh.red_bad[v];
+        total += sh.red_cnt[v];
+    }
+    anybad = uniform(anybad);
+    total = uniform(total);
+    lds_barrier();  // the shared words may be overwritten after this
+    return anybad ? -1 : total;
 }
 
 // Column cache of an owned chunk c: its matrix words mask[w * Mp + 64c +
