@@ -669,16 +669,21 @@ hipError_t launch_nd_sort(const HostPlan &hp, const BatchView &bv, hipStream_t s
     // per compute unit at that register use); otherwise they are streamed.
     const int cus = device_info().cus;
     int q = 0;
-    if (hp.nchunk <= PEEL_CACHE_SLOTS * cus)
-        q = hp.max_W <= 16 * PEEL_WAVES ? 16
-            : hp.max_W <= 32 * PEEL_WAVES ? 32
-            : hp.max_W <= 48 * PEEL_WAVES ? 48 : 0;
+    if (hp.nchunk <= PEEL_CACHE_SLOTS * cus) {
+        for (int c : {16, 24, 32, 40, 48})
+            if (hp.max_W <= c * PEEL_WAVES) {
+                q = c;
+                break;
+            }
+    }
     const int cap = q ? cus : 3 * cus;
     const int peel_blocks = hp.nchunk < cap ? hp.nchunk : cap;
     const dim3 pg(peel_blocks), pb(64 * PEEL_WAVES);
     switch (q) {
         case 16: NSGA3_LAUNCH("peel", k_peel<16>, pg, pb, 0, s, bv, hp.nchunk); break;
+        case 24: NSGA3_LAUNCH("peel", k_peel<24>, pg, pb, 0, s, bv, hp.nchunk); break;
         case 32: NSGA3_LAUNCH("peel", k_peel<32>, pg, pb, 0, s, bv, hp.nchunk); break;
+        case 40: NSGA3_LAUNCH("peel", k_peel<40>, pg, pb, 0, s, bv, hp.nchunk); break;
         case 48: NSGA3_LAUNCH("peel", k_peel<48>, pg, pb, 0, s, bv, hp.nchunk); break;
         default: NSGA3_LAUNCH("peel", k_peel<0>, pg, pb, 0, s, bv, hp.nchunk); break;
     }
