@@ -73,3 +73,19 @@ def test_nonfinite_sets_status():
     F[17, 2] = 0.5
     nsga3.nd_sort(to_dev(F, dev), 50, ws=ws)
     assert ws.status() == nsga3.OK
+
+
+# Sizes that select each way the peel holds a chunk's matrix column: in
+# registers, 16 .. 48 words per wave (W = ceil(M / 64) up to 8 x 16 .. 8 x 48,
+# at most two chunks per compute unit), or streamed from memory every front
+# (W above 384). Each instance has many fronts (radius law "exp").
+@pytest.mark.parametrize("M", [6000, 9000, 15000, 20000, 24500, 25600])
+def test_peel_column_paths(M):
+    dev = device()
+    rng = np.random.default_rng(M)
+    F = wl.objectives(rng, M, 3, "exp")
+    ref_rank, ref_fi = oracle.nd_sort(F, 0)
+    rank, fi = run(F, 0, dev)
+    assert ref_fi[3] > 5  # several fronts
+    assert np.array_equal(rank, ref_rank)
+    assert np.array_equal(fi, ref_fi)
