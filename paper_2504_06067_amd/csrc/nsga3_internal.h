@@ -206,41 +206,76 @@ __device__ __forceinline__ void lds_barrier() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
+// Wave reductions by DPP moves (no LDS round trips). They follow the
+// pattern of wave_incl_scan below: row shifts by 1, 2, 4, 8, then the row
+// broadcasts of lanes 15 and 31; lanes without a source take the operation's
+// identity, and lane 63 ends with the reduction over all 64 lanes, which is
+// then read back into every lane. All lanes must be active.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ unsigned dpp_u32(unsigned identity, unsigned v) {
+    return (unsigned)__builtin_amdgcn_update_dpp((int)identity, (int)v, CTRL, ROWS, 0xf, false);
+}
+
+template <int CTRL, int ROWS>
+__device__ __forceinline__ u64 dpp_u64(u64 identity, u64 v) {
+    const unsigned lo = dpp_u32<CTRL, ROWS>((unsigned)identity, (unsigned)v);
+    const unsigned hi = dpp_u32<CTRL, ROWS>((unsigned)(identity >> 32), (unsigned)(v >> 32));
+    return ((u64)hi << 32) | lo;
+}
+
+__device__ __forceinline__ u64 lane63_u64(u64 v) {
+    const unsigned lo = __builtin_amdgcn_readlane((unsigned)v, 63);
+    const unsigned hi = __builtin_amdgcn_readlane((unsigned)(v >> 32), 63);
+    return ((u64)hi << 32) | lo;
+}
+
+#define NSGA3_DPP_STEPS(STEP) \
+    STEP(0x111, 0xf) STEP(0x112, 0xf) STEP(0x114, 0xf) STEP(0x118, 0xf) STEP(0x142, 0xa) STEP(0x143, 0xc)
+
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
+    static_assert(sizeof(T) == 4 || sizeof(T) == 8, "32- or 64-bit integers");
+    if constexpr (sizeof(T) == 4) {
+        unsigned u = (unsigned)v;
+#define NSGA3_STEP(C, R) u += dpp_u32<C, R>(0u, u);
+        NSGA3_DPP_STEPS(NSGA3_STEP)
+#undef NSGA3_STEP
+        return (T)__builtin_amdgcn_readlane(u, 63);
+    } else {
+        u64 u = (u64)v;
+#define NSGA3_STEP(C, R) u += dpp_u64<C, R>(0ull, u);
+        NSGA3_DPP_STEPS(NSGA3_STEP)
+#undef NSGA3_STEP
+        return (T)lane63_u64(u);
+    }
 }
 
 __device__ __forceinline__ u64 wave_min_u64(u64 v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        u64 w = __shfl_xor(v, o, 64);
-        v = w < v ? w : v;
-    }
-    return v;
+#define NSGA3_STEP(C, R) { const u64 o = dpp_u64<C, R>(~0ull, v); v = o < v ? o : v; }
+    NSGA3_DPP_STEPS(NSGA3_STEP)
+#undef NSGA3_STEP
+    return lane63_u64(v);
 }
 
 __device__ __forceinline__ u64 wave_max_u64(u64 v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        u64 w = __shfl_xor(v, o, 64);
-        v = w > v ? w : v;
-    }
-    return v;
+#define NSGA3_STEP(C, R) { const u64 o = dpp_u64<C, R>(0ull, v); v = o > v ? o : v; }
+    NSGA3_DPP_STEPS(NSGA3_STEP)
+#undef NSGA3_STEP
+    return lane63_u64(v);
 }
 
 __device__ __forceinline__ unsigned wave_min_u32(unsigned v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = min(v, (unsigned)__shfl_xor(v, o, 64));
-    return v;
+#define NSGA3_STEP(C, R) v = min(v, dpp_u32<C, R>(0xffffffffu, v));
+    NSGA3_DPP_STEPS(NSGA3_STEP)
+#undef NSGA3_STEP
+    return __builtin_amdgcn_readlane(v, 63);
 }
 
 __device__ __forceinline__ unsigned wave_max_u32(unsigned v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = max(v, (unsigned)__shfl_xor(v, o, 64));
-    return v;
+#define NSGA3_STEP(C, R) v = max(v, dpp_u32<C, R>(0u, v));
+    NSGA3_DPP_STEPS(NSGA3_STEP)
+#undef NSGA3_STEP
+    return __builtin_amdgcn_readlane(v, 63);
 }
 
 // Inclusive prefix sum over the 64 lanes of a wave.
