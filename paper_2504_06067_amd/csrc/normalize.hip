@@ -75,18 +75,13 @@ __device__ __forceinline__ double read_lane_f64(double v, int L) {
     const unsigned hi = __builtin_amdgcn_readlane((unsigned)(u >> 32), L);
     return __longlong_as_double((long long)(((u64)hi << 32) | lo));
 }
-__device__ __forceinline__ double shfl_f64(double v, int src) {
-    const u64 u = (u64)__double_as_longlong(v);
-    const unsigned lo = (unsigned)__shfl((int)(unsigned)u, src, 64);
-    const unsigned hi = (unsigned)__shfl((int)(unsigned)(u >> 32), src, 64);
-    return __longlong_as_double((long long)(((u64)hi << 32) | lo));
-}
 
 // One wave per instance. E[k][j] =
 // f(e_k)_j - z_j in FP64; E b = 1 is solved by Gaussian elimination with
 // partial pivoting (largest |pivot|, least row on ties), the rows spread over
-// the lanes (lane i holds the row at position i; a swap exchanges two lanes'
-// rows), every product and difference rounded separately; a_k = 1 / b_k
+// the lanes (each row stays in its lane and carries its position; a swap
+// exchanges two positions), every product and difference rounded separately;
+// a_k = 1 / b_k
 // unless degenerate.
 template <int MO>
 __device__ void norm_solve(CInst &I) {
@@ -124,32 +119,35 @@ __device__ void norm_solve(CInst &I) {
         const u64 key = lane < MO ? (u64)__double_as_longlong(fabs(A[j])) : 0ull;
         colmax[j] = __longlong_as_double((long long)wave_max_u64(key));
     }
+    // Rows stay in their lanes; pos is the row's position in the eliminated
+    // matrix (a swap of two positions exchanges two lanes' pos values).
+    int pos = lane;
 #pragma unroll
     for (int c = 0; c < MO; ++c) {
         if (degen) break;
         // pivot: largest |A[i][c]| over positions i >= c, least position on ties
-        const bool cand = lane >= c && lane < MO;
+        const bool cand = lane < MO && pos >= c;
         const u64 key = cand ? (u64)__double_as_longlong(fabs(A[c])) : 0ull;
         const u64 best = wave_max_u64(key);
-        const int piv = __ffsll((long long)ballot(cand && key == best)) - 1;
+        const int piv = (int)wave_min_u32(cand && key == best ? (unsigned)pos : 0xffffffffu);
         const double pv = __longlong_as_double((long long)best);
         if (colmax[c] == 0.0 || pv < 1e-10 * colmax[c]) {
             degen = 1;
             break;
         }
+        const int lp = __ffsll((long long)ballot(lane < MO && pos == piv)) - 1;  // pivot row's lane
+        const int lc = __ffsll((long long)ballot(lane < MO && pos == c)) - 1;    // position c's lane
         if (piv != c) {
-            const int src = lane == c ? piv : (lane == piv ? c : lane);
-#pragma unroll
-            for (int j = 0; j < MO; ++j) A[j] = shfl_f64(A[j], src);
-            rhs = shfl_f64(rhs, src);
+            if (lane == lp) pos = c;
+            else if (lane == lc) pos = piv;
         }
-        const double acc = read_lane_f64(A[c], c);
-        const double rc = read_lane_f64(rhs, c);
-        const bool below = lane > c && lane < MO;
+        const double acc = read_lane_f64(A[c], lp);
+        const double rc = read_lane_f64(rhs, lp);
+        const bool below = lane < MO && pos > c;
         const double f = below ? A[c] / acc : 0.0;
 #pragma unroll
         for (int j = c; j < MO; ++j) {
-            const double acj = read_lane_f64(A[j], c);
+            const double acj = read_lane_f64(A[j], lp);
             if (below) A[j] = __dsub_rn(A[j], __dmul_rn(f, acj));
         }
         if (below) rhs = __dsub_rn(rhs, __dmul_rn(f, rc));
@@ -158,10 +156,11 @@ __device__ void norm_solve(CInst &I) {
     if (!degen) {
 #pragma unroll
         for (int i = MO - 1; i >= 0; --i) {
-            double s = read_lane_f64(rhs, i);
+            const int li = __ffsll((long long)ballot(lane < MO && pos == i)) - 1;  // row at position i
+            double s = read_lane_f64(rhs, li);
 #pragma unroll
-            for (int j = i + 1; j < MO; ++j) s = __dsub_rn(s, __dmul_rn(read_lane_f64(A[j], i), b[j]));
-            b[i] = s / read_lane_f64(A[i], i);
+            for (int j = i + 1; j < MO; ++j) s = __dsub_rn(s, __dmul_rn(read_lane_f64(A[j], li), b[j]));
+            b[i] = s / read_lane_f64(A[i], li);
         }
     }
     // intercepts, or the per-objective maximum when degenerate
@@ -216,18 +215,30 @@ __global__ __launch_bounds__(256) void k_norm_extreme(BatchView bv, int gs, int 
         if (g[k] > g1) { g2 = g1; g1 = g[k]; p1 = k; }
         else if (g[k] > g2) g2 = g[k];
     }
+    // per wave, then per block: one atomic per block and objective (atomics on
+    // one address are performed one after another)
+    __shared__ u64 s_key[4][MO];
+    const int wv = threadIdx.x >> 6;
 #pragma unroll
     for (int k = 0; k < MO; ++k) {
         const float other = (k == p1) ? g2 : g1;
         const float asf = fmaxf(fp[k], other);
-        u64 key = in ? (((u64)__float_as_uint(asf) << 32) | (unsigned)x) : ~0ull;
-        key = wave_min_u64(key);
-        if (lane_id() == 0 && key != ~0ull) atomicMin(&ctrl->ext_key[k], key);
+        const u64 key = in ? (((u64)__float_as_uint(asf) << 32) | (unsigned)x) : ~0ull;
+        const u64 wkey = wave_min_u64(key);
+        if (lane_id() == 0) s_key[wv][k] = wkey;
+    }
+    lds_barrier();
+    if (threadIdx.x < MO) {
+        const int k = threadIdx.x;
+        u64 bkey = s_key[0][k];
+#pragma unroll
+        for (int v = 1; v < 4; ++v) bkey = s_key[v][k] < bkey ? s_key[v][k] : bkey;
+        if (bkey != ~0ull) atomicMin(&ctrl->ext_key[k], bkey);
     }
     (void)gs;
     (void)gn;
     __shared__ int s_last;
-    lds_barrier();  // every wave's minima are issued
+    lds_barrier();  // every minimum of the block is issued
     if (threadIdx.x == 0) {
         // release: this block's minima are performed before the count; the
         // last block acquires them all
