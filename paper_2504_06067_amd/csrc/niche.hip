@@ -517,6 +517,57 @@ __global__ __launch_bounds__(256) void k_niche_pick(BatchView bv) {
     }
     wave_sort(buf, c);
     const int nw = (c + 63) / 64;
+    if (nw <= 64) {
+        // Up to 4096 candidates: lane w holds word w of the remaining set in a
+        // register, and the pick ranks of 64 levels at a time are computed one
+        // per lane (they depend on the level only).
+        const int v0 = c - lane * 64;
+        u64 myrem = lane < nw ? (v0 >= 64 ? ~0ull : ((1ull << v0) - 1)) : 0ull;
+        int own = __popcll(myrem);
+        int kk_lane = 0, kk_base = -1;
+        for (int lev = rj; lev < rj + t; ++lev) {
+            int pos;
+            if (lev == 0) {
+                // first pick of a reference at niche count 0: the nearest candidate
+                u64 best = ~0ull;
+                for (int i = lane; i < c; i += 64) {
+                    const int x = buf[i];
+                    const u64 k = ((u64)__float_as_uint(dist[x]) << 32) | (unsigned)i;
+                    best = k < best ? k : best;
+                }
+                best = wave_min_u64(best);
+                pos = (int)(unsigned)(best & 0xffffffffull);
+            } else {
+                if (kk_base < 0 || lev - kk_base >= 64) {
+                    kk_base = lev;
+                    const int lv = lev + lane;
+                    kk_lane = lv < rj + t ? (int)(tie_key(seed, 2u, (unsigned)j, (unsigned)lv) %
+                                                  (u64)(c - (lv - rj)))
+                                          : 0;
+                }
+                const int kk = __builtin_amdgcn_readlane(kk_lane, lev - kk_base);
+                const int incl = wave_incl_scan(own);
+                const int excl = incl - own;
+                const u64 owner = ballot(excl <= kk && kk < incl);
+                if (owner == 0) break;  // unreachable while the counts are consistent
+                const int L = __ffsll((long long)owner) - 1;
+                const int found = lane * 64 + select_bit(myrem, kk - excl);  // meaningful on lane L
+                pos = __builtin_amdgcn_readlane(found, L);
+            }
+            if (pos < 0 || pos >= c) break;
+            // remove position pos
+            if (lane == (pos >> 6)) {
+                myrem &= ~(1ull << (pos & 63));
+                own -= 1;
+            }
+            if (lane == 0) {
+                const int x = buf[pos];
+                picked[x] = 1;
+                atomicAdd(&tcnt[x / COMPACT_TILE], 1);
+            }
+        }
+        return;
+    }
     for (int w = lane; w < nw; w += 64) {
         const int v = c - w * 64;
         rem[w] = v >= 64 ? ~0ull : ((1ull << v) - 1);
@@ -555,7 +606,7 @@ __global__ __launch_bounds__(256) void k_niche_pick(BatchView bv) {
                     k2 -= pc;
                 }
             }
-            pos = __shfl(found, L, 64);
+            pos = __builtin_amdgcn_readlane(found, L);
         }
         if (pos < 0 || pos >= c) break;
         // remove position pos
