@@ -293,6 +293,10 @@ __global__ __launch_bounds__(256) void k_dominance(BatchView bv, int gs, int gn,
 //
 // Control flow is wave-uniform around every workgroup barrier: wave 0 makes
 // the scheduling decisions with all its lanes and shares them through LDS.
+// Consecutive owned chunks of one instance share one wait, so no barrier
+// separates wave 0's update of a chunk's running total from the other waves'
+// read of it; the totals are therefore kept twice, by the parity of the
+// front, and a wave never reads a value written for the front after.
 // Barriers order LDS only (they do not wait for global stores in flight).
 constexpr int PEEL_WAVES = 8;
 constexpr int PEEL_OWN_CAP = 1024;
@@ -310,7 +314,9 @@ __device__ __forceinline__ u64 *front_slot(u64 *ring, int W, int k) {
 struct PeelShared {
     int own_b[PEEL_OWN_CAP];    // instance of each owned chunk
     int own_c[PEEL_OWN_CAP];    // chunk within its instance
-    int own_cum[PEEL_OWN_CAP];  // points in the instance's fronts seen so far (-1: done)
+    // points in the instance's fronts before front k - 1 (-1: done), read
+    // from [k & 1] and written to [(k + 1) & 1] while front k is processed
+    int own_cum[2][PEEL_OWN_CAP];
     u64 own_alive[PEEL_OWN_CAP];  // its points not yet ranked
     u64 dead[PEEL_LDS_ALIVE];   // members of the awaited front, per block of 64 points
     int part[PEEL_CACHE_SLOTS][PEEL_WAVES][64];  // per-wave partial decrements of a chunk's counts
@@ -571,7 +577,7 @@ __global__ __launch_bounds__(64 * PEEL_WAVES) void k_peel(BatchView bv, int nchu
             if (Q > 0 && nown < PEEL_CACHE_SLOTS) sh.cleft[nown][lane] = bv.tab[b].P.nd[c * 64 + lane];
             sh.own_b[nown] = b;
             sh.own_c[nown] = c;
-            sh.own_cum[nown] = 0;
+            sh.own_cum[1][nown] = 0;
         }
         ++nown;
         if (nown == PEEL_OWN_CAP) break;
@@ -588,13 +594,17 @@ __global__ __launch_bounds__(64 * PEEL_WAVES) void k_peel(BatchView bv, int nchu
     }
 
     for (int k = 1;; ++k) {
+        const int cur = k & 1, nxt = cur ^ 1;
         int active = 0;
         int awaited = -1, size = 0;  // instance whose front k - 1 was last awaited
         for (int q = 0; q < nown; ++q) {
             const int b = uniform(sh.own_b[q]);
             const int c = uniform(sh.own_c[q]);
-            const int cum_prev = uniform(sh.own_cum[q]);
-            if (cum_prev < 0) continue;  // this instance finished
+            const int cum_prev = uniform(sh.own_cum[cur][q]);
+            if (cum_prev < 0) {  // this instance finished
+                if (wv == 0) sh.own_cum[nxt][q] = -1;
+                continue;
+            }
             CInst &I = bv.tab[b];
             const bool staged = uniform(I.W) <= PEEL_LDS_ALIVE;
             // wait for front k - 1 of the instance (already staged when the
@@ -611,16 +621,16 @@ __global__ __launch_bounds__(64 * PEEL_WAVES) void k_peel(BatchView bv, int nchu
                     I.front_info[1] = cum_prev;
                     I.front_info[2] = I.n_stop - cum_prev;
                     I.front_info[3] = k;
-                    sh.own_cum[q] = -1;
+                    sh.own_cum[nxt][q] = -1;
                 }
                 continue;
             }
-            if (wv == 0) sh.own_cum[q] = cum;
+            if (wv == 0) sh.own_cum[nxt][q] = cum;
             if constexpr (Q > 0) {
                 static_assert(PEEL_CACHE_SLOTS == 2, "one branch per cached slot");
                 // both cached chunks of one instance, together
-                if (q == 0 && nown > 1 && uniform(sh.own_b[1]) == b && uniform(sh.own_cum[1]) >= 0) {
-                    if (wv == 0) sh.own_cum[1] = cum;
+                if (q == 0 && nown > 1 && uniform(sh.own_b[1]) == b && uniform(sh.own_cum[cur][1]) >= 0) {
+                    if (wv == 0) sh.own_cum[nxt][1] = cum;
                     peel_pair<Q>(I, k, c, uniform(sh.own_c[1]), sh, col0, col1);
                     active = 1;
                     q = 1;

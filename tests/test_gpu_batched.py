@@ -123,6 +123,36 @@ def test_uneven_batch_full_size():
         check_oracle(insts[b], got[b])
 
 
+def test_streamed_peel_repeated():
+    """Large multi-front instances whose peel streams matrix columns (more
+    chunks than the register caches hold), so that workgroups own several
+    chunks of one instance: every call of the batch, and every call of the
+    plain path, gives the same ranks and selection."""
+    dev = device()
+    shapes = [(79048, 3), (85532, 5), (60000, 10), (45000, 15), (70000, 3)]
+    probs = []
+    for i, (M, m) in enumerate(shapes):
+        F = to_dev(wl.objectives(np.random.default_rng(M), M, m, "exp"), dev)
+        Z = to_dev(wl.served_refs(m), dev)
+        probs.append(dict(F=F, Z=Z, N=M // 2, seed=11 + i))
+    plain = []
+    for p in probs:
+        o = nsga3.select(p["F"], p["Z"], p["N"], p["seed"], intermediates=True)
+        plain.append({k: to_np(o[k]).copy() for k in ("selected", "rank")})
+    bt = nsga3.Batch(probs, intermediates=True)
+    for call in range(24):
+        bt.run()
+        torch.cuda.synchronize()
+        assert bt.status() == [nsga3.OK] * len(probs), call
+        for b in range(len(probs)):
+            assert np.array_equal(to_np(bt.rank[b]), plain[b]["rank"]), (call, b)
+            assert np.array_equal(to_np(bt.selected[b]), plain[b]["selected"]), (call, b)
+    p = probs[0]
+    for call in range(8):
+        o = nsga3.select(p["F"], p["Z"], p["N"], p["seed"], intermediates=True)
+        assert np.array_equal(to_np(o["rank"]), plain[0]["rank"]), call
+
+
 def test_graph_replay():
     dev = device()
     insts = mixed_instances(5, 6)
