@@ -101,13 +101,6 @@ __device__ __forceinline__ unsigned shift_in(unsigned a, u64 mask) {
     return r;
 }
 
-// The value of lane L (wave-uniform) of a 64-bit register pair.
-__device__ __forceinline__ u64 read_lane64(u64 x, int L) {
-    const unsigned lo = __builtin_amdgcn_readlane((unsigned)x, L);
-    const unsigned hi = __builtin_amdgcn_readlane((unsigned)(x >> 32), L);
-    return ((u64)hi << 32) | lo;
-}
-
 // Lane R of `old` takes the wave-uniform value v.
 template <int R>
 __device__ __forceinline__ unsigned write_lane(unsigned old, unsigned v) {
