@@ -26,6 +26,8 @@ def _load():
     P = ctypes.c_void_p
     i32 = ctypes.c_int
     u64 = ctypes.c_uint64
+    lib.oracle_set_threads.argtypes = [i32]
+    lib.oracle_set_threads.restype = i32
     lib.oracle_splitmix64.argtypes = [u64]
     lib.oracle_splitmix64.restype = u64
     lib.oracle_key.argtypes = [u64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32]
@@ -49,6 +51,12 @@ def _p(a):
 def _check(rc, what):
     if rc != 0:
         raise RuntimeError(f"{what} failed with code {rc}")
+
+
+def set_threads(n):
+    """Threads for the dominance and association loops (1 = serial, the
+    default). Results are identical for every count. Returns the count set."""
+    return int(_load().oracle_set_threads(int(n)))
 
 
 def splitmix64(x):

@@ -48,6 +48,17 @@ uint64_t oracle_key(uint64_t seed, uint32_t tag, uint32_t j, uint32_t L) {
     return oracle_splitmix64(seed ^ oracle_splitmix64(packed));
 }
 
+/* ---------------------------------------------------------------- threads */
+
+/* Threads for the two per-row loops (dominance, association); 1 = the plain
+ * serial code. Every result is the same for any count. */
+static int g_threads = 1;
+
+int oracle_set_threads(int n) {
+    g_threads = n < 1 ? 1 : n;
+    return g_threads;
+}
+
 /* ----------------------------------------------------- non-dominated sort */
 
 /* a dominates b (minimization): a is no worse in every objective and strictly
@@ -96,16 +107,36 @@ int oracle_nd_sort(const float *F, int M, int m, int n_stop,
     int *nxt = (int *)malloc((size_t)M * sizeof(int));
     if (!S || !n || !full || !cur || !nxt) return -5;
 
-    for (int p = 0; p < M; ++p) {
-        for (int q = p + 1; q < M; ++q) {
-            if (dominates(F + (long)p * m, F + (long)q * m, m)) {
-                if (ivec_push(&S[p], q)) return -5;
-                n[q] += 1;
-            } else if (dominates(F + (long)q * m, F + (long)p * m, m)) {
-                if (ivec_push(&S[q], p)) return -5;
-                n[p] += 1;
+    if (g_threads <= 1) {
+        for (int p = 0; p < M; ++p) {
+            for (int q = p + 1; q < M; ++q) {
+                if (dominates(F + (long)p * m, F + (long)q * m, m)) {
+                    if (ivec_push(&S[p], q)) return -5;
+                    n[q] += 1;
+                } else if (dominates(F + (long)q * m, F + (long)p * m, m)) {
+                    if (ivec_push(&S[q], p)) return -5;
+                    n[p] += 1;
+                }
             }
         }
+    } else {
+        /* Several threads: each row p is built on its own (S_p and n_p from
+         * all q), which compares every ordered pair instead of every
+         * unordered one but writes no shared state. S_p comes out in the
+         * same ascending order as above. */
+        int fail = 0;
+#pragma omp parallel for schedule(dynamic, 16) num_threads(g_threads) reduction(| : fail)
+        for (int p = 0; p < M; ++p) {
+            for (int q = 0; q < M; ++q) {
+                if (q == p) continue;
+                if (dominates(F + (long)p * m, F + (long)q * m, m)) {
+                    if (ivec_push(&S[p], q)) fail = 1;
+                } else if (dominates(F + (long)q * m, F + (long)p * m, m)) {
+                    n[p] += 1;
+                }
+            }
+        }
+        if (fail) return -5;
     }
 
     /* Peel fronts: F_0 = {p : n_p = 0}; removing F_k decrements the counts of
@@ -272,6 +303,9 @@ int oracle_associate(const double *Fn, const int *rank, const int *front_info,
         s = sqrt(s);
         for (int k = 0; k < m; ++k) W[(long)j * m + k] = Z[(long)j * m + k] / s;
     }
+    /* Rows are independent: with several threads each x is still computed
+     * by the loop body below, unchanged. */
+#pragma omp parallel for schedule(dynamic, 64) num_threads(g_threads > 1 ? g_threads : 1)
     for (int x = 0; x < M; ++x) {
         if (!in_st(rank, l, x)) { pi[x] = -1; dist[x] = -1.0; continue; }
         const double *f = Fn + (long)x * m;

@@ -33,6 +33,10 @@
 extern "C" {
 #endif
 
+/* Threads used by the dominance and association loops (default 1, the plain
+ * serial loops). Results do not depend on it. Returns the count set. */
+int oracle_set_threads(int n);
+
 /* SplitMix64 output function (Steele, Lea & Flood 2014). */
 uint64_t oracle_splitmix64(uint64_t x);
 /* Tie-break key: sm64(seed ^ sm64((tag << 62) | (L << 32) | j)). */

@@ -7,8 +7,7 @@ import numpy as np
 import pytest
 import torch
 
-import oracle
-from gpu_util import device, to_dev, to_np
+from gpu_util import device, select_parity, to_dev, to_np
 from paper_2504_06067_amd import nsga3
 from paper_2504_06067_amd import workloads as wl
 
@@ -61,14 +60,12 @@ def same(a, b):
     return all(np.array_equal(a[k], b[k]) for k in KEYS)
 
 
-def check_oracle(q, g):
-    ref = oracle.select(q["F"], q["Z"], q["N"], q["seed"])
-    assert np.array_equal(g["rank"], ref["rank"])
-    _, fi = oracle.nd_sort(q["F"], q["N"])
-    chained = oracle.niche(g["rank"], fi, g["pi"], g["dist"].astype(np.float64), q["H"], q["N"],
-                           q["seed"])
-    assert np.array_equal(g["selected"], chained)
-    assert np.array_equal(g["selected"], ref["selected"]) or np.any(g["pi"] != ref["pi"])
+def check_oracle(q, g, dev):
+    """The FP64 oracle's bar for a batched result (see select_parity)."""
+    r = select_parity(q, g, dev)
+    assert r["ext_ties"] == 0
+    assert r["pi_ties"] <= max(2, 1e-3 * r["n_st"])
+    return r
 
 
 @pytest.mark.parametrize("seed", [0, 1, 2])
@@ -78,7 +75,7 @@ def test_batched_equals_plain_and_oracle(seed):
     got = run_batched(insts, dev)
     for q, g in zip(insts, got):
         assert same(g, run_plain(q, dev)), (q["M"], q["m"], q["N"])
-        check_oracle(q, g)
+        check_oracle(q, g, dev)
 
 
 def test_tile_invariance():
@@ -120,7 +117,7 @@ def test_uneven_batch_full_size():
     for q, g in zip(insts, got):
         assert same(g, run_plain(q, dev)), (q["M"], q["m"])
     for b in sorted(range(64), key=lambda i: insts[i]["M"])[:3]:
-        check_oracle(insts[b], got[b])
+        check_oracle(insts[b], got[b], dev)
 
 
 def test_streamed_peel_repeated():

@@ -88,3 +88,41 @@ def test_degenerate():
     assert int(to_np(out["degenerate"])[0]) == 1
     ref = oracle.normalize(F, rank, fi)
     assert np.array_equal(to_np(out["intercept"]), ref["intercept"])
+
+
+# The oracle's pinned degeneracy and tie cases (dyadic inputs, exact in
+# float32): the GPU takes the same branch and gives the same intercepts.
+def _run_all_st(F, dev):
+    M = len(F)
+    rank = np.zeros(M, np.int32)
+    fi = np.array([0, 0, M, 1], np.int32)
+    out = nsga3.normalize(to_dev(F, dev), to_dev(rank, dev), to_dev(fi, dev))
+    ref = oracle.normalize(F, rank, fi)
+    return ({k: to_np(v) for k, v in out.items()}, ref)
+
+
+def test_asf_tie_least_index():
+    dev = device()
+    t = 2.0 ** -10
+    base = [(1.0, 1.0, 1.0), (0.0, 1.0, 0.5), (0.75, 0.0, 1.0)]
+    for lo, hi in ((0.5, 0.25), (0.25, 0.5)):
+        F = np.array(base + [(lo, t, 0.0), (hi, t, 0.0)], np.float32)
+        out, ref = _run_all_st(F, dev)
+        assert int(out["extreme"][0]) == 3 == int(ref["extreme"][0])
+        assert np.array_equal(out["extreme"], ref["extreme"])
+
+
+@pytest.mark.parametrize("e3,extra,degen", [
+    ((0.875, 0.875, 0.125), [], 1),            # b_3 = -6
+    ((0.5, 0.5, 0.125), [], 1),                # b_3 = 0
+    ((0.25, 0.25, 2.0 ** -20), [(2.0, 2.0, 4.0)], 1),  # a_3 = 2^-19 < 1e-6 * 4
+    ((0.25, 0.25, 2.0 ** -20), [(2.0, 2.0, 1.0)], 0),  # a_3 = 2^-19 >= 1e-6 * 1
+])
+def test_degeneracy_branches(e3, extra, degen):
+    dev = device()
+    F = np.array([(1.0, 0.0, 0.0), (0.0, 1.0, 0.0), e3, *extra], np.float32)
+    out, ref = _run_all_st(F, dev)
+    assert ref["degenerate"] == degen
+    assert int(out["degenerate"][0]) == degen
+    assert np.array_equal(out["extreme"], ref["extreme"])
+    assert np.array_equal(out["intercept"], ref["intercept"])

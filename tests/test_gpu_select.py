@@ -1,12 +1,13 @@
-"""End-to-end parity of nsga3_select: ranks bit-exact; the selection equals
-the oracle's (FP64 all the way) unless an upstream FP32 near-tie is flagged,
-and always equals the oracle's niching of the GPU's own (rank, pi, dist)."""
+"""End-to-end parity of nsga3_select against the FP64 oracle: ranks
+bit-exact; extreme points exact or FP64 ASF near-ties; every association
+mismatch of the select path's own (fused) association a near-tie within
+1e-6 ||f_n||, with the distance within 1e-6 ||f_n||; the selection equal to
+the oracle's niching of the GPU's own (rank, pi, dist), and equal to the
+pure-FP64 oracle whenever nothing was flagged."""
 import numpy as np
 import pytest
-import torch
 
-import oracle
-from gpu_util import device, to_dev, to_np
+from gpu_util import device, select_parity, to_dev, to_np
 from paper_2504_06067_amd import nsga3
 from paper_2504_06067_amd import workloads as wl
 
@@ -20,28 +21,23 @@ def run(inst, dev, ws=None):
 
 
 def check(inst, dev):
-    g = run(inst, dev)
-    ref = oracle.select(inst["F"], inst["Z"], inst["N"], inst["seed"])
-    assert np.array_equal(g["rank"], ref["rank"])
-    _, fi = oracle.nd_sort(inst["F"], inst["N"])
-    chained = oracle.niche(g["rank"], fi, g["pi"], g["dist"].astype(np.float64), inst["H"],
-                           inst["N"], inst["seed"])
-    assert np.array_equal(g["selected"], chained)
-    return np.array_equal(g["selected"], ref["selected"]), int(np.sum(g["pi"] != ref["pi"]))
+    return select_parity(inst, run(inst, dev), dev)
 
 
 @pytest.mark.parametrize("seed", range(8))
 def test_small_workload(seed):
     dev = device()
-    same, npi = check(wl.plain_instance("small", seed), dev)
-    assert same or npi > 0
+    r = check(wl.plain_instance("small", seed), dev)
+    assert r["ext_ties"] == 0
+    assert r["pi_ties"] <= 2
 
 
 @pytest.mark.parametrize("name,M", [("large", 2000), ("large", None), ("many_objective", 4000)])
 def test_larger_workloads(name, M):
     dev = device()
-    same, npi = check(wl.plain_instance(name, 0, M=M), dev)
-    assert same or npi > 0
+    r = check(wl.plain_instance(name, 0, M=M), dev)
+    assert r["ext_ties"] == 0
+    assert r["pi_ties"] <= max(2, 1e-3 * r["n_st"])
 
 
 @pytest.mark.parametrize("M,m,p", [(2, 2, 1), (3, 2, 3), (65, 3, 4), (130, 5, 3), (257, 16, 1)])
@@ -52,7 +48,8 @@ def test_edge_shapes(M, m, p):
     Z = wl.das_dennis(m, p)
     for N in sorted({1, M // 2 or 1, M}):
         inst = dict(F=F, Z=Z, N=N, H=len(Z), seed=N)
-        check(inst, dev)
+        r = check(inst, dev)
+        assert r["ext_ties"] == 0 and r["pi_ties"] == 0 and r["identical"], (N, r)
 
 
 def test_repeatable_and_status_ok():

@@ -130,3 +130,22 @@ def test_rejects_nonfinite():
     F[2, 1] = np.nan
     with pytest.raises(RuntimeError):
         oracle.nd_sort(F, 0)
+
+
+@pytest.mark.parametrize("name,M,seed", [("small", None, 0), ("large", 3000, 1),
+                                         ("many_objective", 2500, 2)])
+def test_threads_do_not_change_results(name, M, seed):
+    # the multi-threaded dominance (ordered pairs, row by row) and association
+    # loops give the serial oracle's results exactly
+    inst = wl.plain_instance(name, seed, M=M)
+    F = inst["F"].copy()
+    F[7] = F[3]  # a duplicate pair: mutually non-dominating
+    try:
+        oracle.set_threads(1)
+        a = oracle.select(F, inst["Z"], inst["N"], inst["seed"])
+        oracle.set_threads(4)
+        b = oracle.select(F, inst["Z"], inst["N"], inst["seed"])
+    finally:
+        oracle.set_threads(1)
+    for k in a:
+        assert np.array_equal(a[k], b[k]), k

@@ -93,3 +93,68 @@ def test_only_st_rows_count():
     np.testing.assert_array_equal(r["ideal"], F[:20].astype(np.float64).min(axis=0))
     assert np.all(r["extreme"] < 20)
     assert np.all(np.isnan(r["Fn"][20:]))
+
+
+# Hand-built extreme sets (dyadic values, so every translated objective and
+# every 1e6 multiple below is exact in float32 and float64; ideal point 0).
+# Axis points e1 = (1, 0, 0) and e2 = (0, 1, 0) fix b_1 = b_2 = 1; the third
+# row decides b_3 of the hyperplane f . b = 1 through the extreme points.
+def three_extremes(e3, extra=()):
+    rows = [(1.0, 0.0, 0.0), (0.0, 1.0, 0.0), e3, *extra]
+    return np.array(rows, np.float32)
+
+
+def test_asf_tie_goes_to_least_index():
+    # Two points whose axis-1 ASF is the same product 1e6 * 2^-10 (their first
+    # objectives differ and stay below it): the least index is the extreme,
+    # in either order of the two (a "last index" rule, or an ASF without the
+    # 1e6 factor, picks index 4 in one of the orders).
+    t = 2.0 ** -10
+    base = [(1.0, 1.0, 1.0), (0.0, 1.0, 0.5), (0.75, 0.0, 1.0)]
+    for lo, hi in ((0.5, 0.25), (0.25, 0.5)):
+        F = np.array(base + [(lo, t, 0.0), (hi, t, 0.0)], np.float32)
+        rank, fi = all_st(len(F))
+        r = oracle.normalize(F, rank, fi)
+        assert np.array_equal(r["ideal"], np.zeros(3))
+        assert r["extreme"][0] == 3, (lo, hi, r["extreme"])
+
+
+def test_negative_intercept_is_degenerate():
+    # e3 = (7/8, 7/8, 1/8): ASF_3 = 875000 < 1e6, so it is the axis-3 extreme;
+    # the plane through the three rows has b_3 = (1 - 7/4) / (1/8) = -6 <= 0
+    F = three_extremes((0.875, 0.875, 0.125))
+    r = oracle.normalize(F, *all_st(3))
+    assert list(r["extreme"]) == [0, 1, 2]
+    z = np.zeros(3)
+    E = F.astype(np.float64) - z
+    b = np.linalg.solve(E, np.ones(3))
+    assert b[2] == -6.0  # the branch is reached by a solvable, non-singular system
+    assert r["degenerate"] == 1
+    assert np.array_equal(r["intercept"], np.array([1.0, 1.0, 0.125]))
+
+
+def test_zero_b_is_degenerate():
+    # e3 = (1/2, 1/2, 1/8) lies on f1 + f2 = 1: b_3 = 0 exactly (a_3 infinite)
+    F = three_extremes((0.5, 0.5, 0.125))
+    r = oracle.normalize(F, *all_st(3))
+    assert list(r["extreme"]) == [0, 1, 2]
+    assert r["degenerate"] == 1
+    assert np.array_equal(r["intercept"], np.array([1.0, 1.0, 0.125]))
+
+
+@pytest.mark.parametrize("far,degen", [(4.0, 1), (1.0, 0)])
+def test_tiny_intercept_relative_to_span(far, degen):
+    # e3 = (1/4, 1/4, 2^-20) gives b_3 = (1 - 1/2) / 2^-20, i.e. a_3 = 2^-19
+    # (about 1.9e-6). A fourth point (2, 2, far) sets max f'_3 = far without
+    # being an extreme (its ASF values are 2e6 or more). The intercept is
+    # rejected iff a_3 < 1e-6 * far: relative, so far = 4 rejects it and
+    # far = 1 keeps it (an absolute 1e-6 threshold would keep both).
+    c = 2.0 ** -20
+    F = three_extremes((0.25, 0.25, c), extra=[(2.0, 2.0, far)])
+    r = oracle.normalize(F, *all_st(4))
+    assert list(r["extreme"]) == [0, 1, 2]
+    assert r["degenerate"] == degen
+    if degen:
+        assert np.array_equal(r["intercept"], np.array([2.0, 2.0, far]))
+    else:
+        assert np.array_equal(r["intercept"], np.array([1.0, 1.0, 2.0 ** -19]))
