@@ -17,7 +17,9 @@
  *    until that work completes.
  *  - Arguments are validated on the host before anything is enqueued. On
  *    NSGA3_EINVAL / NSGA3_EWORKSPACE nothing is enqueued.
- *  - Objectives are minimized. F is row-major [M][m] float32, m in [2, 16],
+ *  - Objectives are minimized. F is row-major [M][m] float32, m in [2, 512]
+ *    (kernels specialized per m up to 16; general kernels above, the
+ *    many-objective regime of the paper's objective-scaling experiment),
  *    2 <= M <= 2^20. Z is row-major [H][m] float32 with finite, non-negative,
  *    non-zero rows (e.g. a Das-Dennis lattice); the library scales each row
  *    to unit length itself.
@@ -64,7 +66,7 @@ enum {
 };
 
 #define NSGA3_UNRANKED 0x7fffffff
-#define NSGA3_MAX_OBJECTIVES 16
+#define NSGA3_MAX_OBJECTIVES 512
 #define NSGA3_MAX_POINTS (1 << 20)
 
 /* Workspace size in bytes for one selection of M merged points, m objectives,
@@ -217,7 +219,8 @@ int nsga3_read_status_batched(const nsga3_instance *inst, int32_t B, const void 
 #define NSGA3_EVOLVE_GENERATION 0
 #define NSGA3_EVOLVE_POPULATION 1
 #define NSGA3_EVOLVE_INIT 2
-#define NSGA3_MAX_DECISION 64
+#define NSGA3_MAX_EVOLVE_OBJECTIVES 16
+#define NSGA3_MAX_DECISION 1024  /* the random draws index variables with 10 bits */
 
 typedef struct nsga3_evolve_slot {
     const float *X_old;   /* [*][d] previous merged decision vectors (read) */
@@ -226,7 +229,8 @@ typedef struct nsga3_evolve_slot {
     float *X_new;         /* [2N][d] (GENERATION) or [N][d] (write) */
     float *F_new;         /* [2N][m] or [N][m] (write) */
     const float *A;       /* [m][d-1] objective map matrix (read) */
-    int32_t N, d, m;      /* N in [1, 2^19], d in [2, NSGA3_MAX_DECISION], m in [2, 16] */
+    int32_t N, d, m;      /* N in [1, 2^19], d in [2, NSGA3_MAX_DECISION],
+                           * m in [2, NSGA3_MAX_EVOLVE_OBJECTIVES] */
     int32_t generation;   /* in [0, 65535] */
     uint64_t seed;
     int32_t mode;         /* NSGA3_EVOLVE_* */

@@ -182,46 +182,57 @@ static int in_st(const int *rank, int l, int x) { return rank[x] >= 0 && rank[x]
  * |pivot|, lowest row on ties). Returns 1 if a pivot is below 1e-10 times the
  * largest magnitude of its column in the original matrix. */
 static int solve_hyperplane(int m, const double *E, double *b) {
-    double A[16][16], r[16], colmax[16];
+    double *A = (double *)malloc((size_t)m * m * sizeof(double));
+    double *r = (double *)malloc((size_t)m * sizeof(double));
+    double *colmax = (double *)malloc((size_t)m * sizeof(double));
+    int singular = 0;
+    if (!A || !r || !colmax) { free(A); free(r); free(colmax); return -1; }
+#define A(i, j) A[(size_t)(i) * m + (j)]
     for (int i = 0; i < m; ++i) {
         r[i] = 1.0;
-        for (int j = 0; j < m; ++j) A[i][j] = E[i * m + j];
+        for (int j = 0; j < m; ++j) A(i, j) = E[i * m + j];
     }
     for (int j = 0; j < m; ++j) {
         colmax[j] = 0.0;
         for (int i = 0; i < m; ++i)
             if (fabs(E[i * m + j]) > colmax[j]) colmax[j] = fabs(E[i * m + j]);
     }
-    for (int c = 0; c < m; ++c) {
+    for (int c = 0; c < m && !singular; ++c) {
         int piv = c;
         for (int i = c + 1; i < m; ++i)
-            if (fabs(A[i][c]) > fabs(A[piv][c])) piv = i;
-        if (colmax[c] == 0.0 || fabs(A[piv][c]) < 1e-10 * colmax[c]) return 1;
+            if (fabs(A(i, c)) > fabs(A(piv, c))) piv = i;
+        if (colmax[c] == 0.0 || fabs(A(piv, c)) < 1e-10 * colmax[c]) { singular = 1; break; }
         if (piv != c) {
-            for (int j = 0; j < m; ++j) { double t = A[c][j]; A[c][j] = A[piv][j]; A[piv][j] = t; }
+            for (int j = 0; j < m; ++j) { double t = A(c, j); A(c, j) = A(piv, j); A(piv, j) = t; }
             double t = r[c]; r[c] = r[piv]; r[piv] = t;
         }
         for (int i = c + 1; i < m; ++i) {
-            double f = A[i][c] / A[c][c];
-            for (int j = c; j < m; ++j) A[i][j] -= f * A[c][j];
+            double f = A(i, c) / A(c, c);
+            for (int j = c; j < m; ++j) A(i, j) -= f * A(c, j);
             r[i] -= f * r[c];
         }
     }
-    for (int i = m - 1; i >= 0; --i) {
+    for (int i = m - 1; i >= 0 && !singular; --i) {
         double s = r[i];
-        for (int j = i + 1; j < m; ++j) s -= A[i][j] * b[j];
-        b[i] = s / A[i][i];
+        for (int j = i + 1; j < m; ++j) s -= A(i, j) * b[j];
+        b[i] = s / A(i, i);
     }
-    return 0;
+#undef A
+    free(A); free(r); free(colmax);
+    return singular;
 }
 
 int oracle_normalize(const float *F, const int *rank, const int *front_info,
                      int M, int m, double *Fn, double *ideal,
                      double *intercept, int *extreme, int *degenerate) {
     if (!F || !rank || !front_info || !Fn || !ideal || !intercept || !extreme ||
-        !degenerate || M < 1 || m < 2 || m > 16)
+        !degenerate || M < 1 || m < 2 || m > ORACLE_MAX_OBJECTIVES)
         return -1;
     int l = front_info[0];
+    double *fmax = (double *)malloc((size_t)m * sizeof(double));
+    double *E = (double *)malloc((size_t)m * m * sizeof(double));
+    double *b = (double *)malloc((size_t)m * sizeof(double));
+    if (!fmax || !E || !b) { free(fmax); free(E); free(b); return -5; }
 
     /* Ideal point z over S_t. */
     for (int k = 0; k < m; ++k) ideal[k] = INFINITY;
@@ -231,7 +242,6 @@ int oracle_normalize(const float *F, const int *rank, const int *front_info,
                 if ((double)F[(long)x * m + k] < ideal[k]) ideal[k] = F[(long)x * m + k];
 
     /* Largest translated objective over S_t (the fallback intercept). */
-    double fmax[16];
     for (int k = 0; k < m; ++k) fmax[k] = 0.0;
     for (int x = 0; x < M; ++x)
         if (in_st(rank, l, x))
@@ -260,11 +270,11 @@ int oracle_normalize(const float *F, const int *rank, const int *front_info,
 
     /* Intercepts: the hyperplane sum_j f'_j * b_j = 1 through the m extreme
      * points; a_j = 1 / b_j. */
-    double E[256], b[16];
     for (int k = 0; k < m; ++k)
         for (int j = 0; j < m; ++j)
             E[k * m + j] = (double)F[(long)extreme[k] * m + j] - ideal[j];
     int degen = solve_hyperplane(m, E, b);
+    if (degen < 0) { free(fmax); free(E); free(b); return -5; }
     for (int k = 0; k < m && !degen; ++k) {
         if (!(b[k] > 0.0)) { degen = 1; break; }
         double a = 1.0 / b[k];
@@ -280,6 +290,7 @@ int oracle_normalize(const float *F, const int *rank, const int *front_info,
         if (in_st(rank, l, x))
             for (int k = 0; k < m; ++k)
                 Fn[(long)x * m + k] = ((double)F[(long)x * m + k] - ideal[k]) / intercept[k];
+    free(fmax); free(E); free(b);
     return 0;
 }
 
@@ -407,16 +418,19 @@ int oracle_niche(const int *rank, const int *front_info, const int *pi,
 int oracle_select(const float *F, int M, int m, const float *Z, int H, int N,
                   uint64_t seed, int *selected, int *rank_out, int *pi_out,
                   double *dist_out) {
-    if (!F || !Z || !selected || M < 2 || m < 2 || m > 16 || H < 1 || N < 1 || N > M)
+    if (!F || !Z || !selected || M < 2 || m < 2 || m > ORACLE_MAX_OBJECTIVES || H < 1 || N < 1 ||
+        N > M)
         return -1;
     int fi[4];
     int *rank = (int *)malloc((size_t)M * sizeof(int));
     int *pi = (int *)malloc((size_t)M * sizeof(int));
     double *dist = (double *)malloc((size_t)M * sizeof(double));
     double *Fn = (double *)calloc((size_t)M * m, sizeof(double));
-    double ideal[16], icpt[16];
-    int ext[16], degen;
-    int rc = (rank && pi && dist && Fn) ? 0 : -5;
+    double *ideal = (double *)malloc((size_t)m * sizeof(double));
+    double *icpt = (double *)malloc((size_t)m * sizeof(double));
+    int *ext = (int *)malloc((size_t)m * sizeof(int));
+    int degen;
+    int rc = (rank && pi && dist && Fn && ideal && icpt && ext) ? 0 : -5;
     if (!rc) rc = oracle_nd_sort(F, M, m, N, rank, fi);
     if (!rc) rc = oracle_normalize(F, rank, fi, M, m, Fn, ideal, icpt, ext, &degen);
     if (!rc) rc = oracle_associate(Fn, rank, fi, M, m, Z, H, pi, dist);
@@ -424,6 +438,6 @@ int oracle_select(const float *F, int M, int m, const float *Z, int H, int N,
     if (!rc && rank_out) memcpy(rank_out, rank, (size_t)M * sizeof(int));
     if (!rc && pi_out) memcpy(pi_out, pi, (size_t)M * sizeof(int));
     if (!rc && dist_out) memcpy(dist_out, dist, (size_t)M * sizeof(double));
-    free(rank); free(pi); free(dist); free(Fn);
+    free(rank); free(pi); free(dist); free(Fn); free(ideal); free(icpt); free(ext);
     return rc;
 }

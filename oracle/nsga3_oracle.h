@@ -28,6 +28,7 @@
 #include <stdint.h>
 
 #define ORACLE_UNRANKED 0x7fffffff
+#define ORACLE_MAX_OBJECTIVES 512
 
 #ifdef __cplusplus
 extern "C" {

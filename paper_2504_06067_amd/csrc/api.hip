@@ -27,7 +27,7 @@ Layout make_layout(int M, int m, int H, int N) {
     const size_t Mp = (size_t)L.Mp, W = (size_t)L.W, Hp = (size_t)L.Hp;
     size_t o = 0;
     auto take = [&o](size_t bytes) { size_t at = o; o += up256(bytes); return at; };
-    L.ctrl = take(4096);
+    L.ctrl = take(sizeof(Ctrl));
     L.ft = take((size_t)m * Mp * 4);
     L.nd = take(Mp * 4);
     L.mask = take(W * Mp * 8);
@@ -48,6 +48,8 @@ Layout make_layout(int M, int m, int H, int N) {
     L.picked = take(Mp * 4);
     L.tcnt = take((Mp + COMPACT_TILE - 1) / COMPACT_TILE * 4);
     L.remain = take((W + (size_t)H + 2) * 8);
+    L.adone = take(W * 4);
+    L.emat = take(m > NARROW_M ? ((size_t)m * m + 3 * (size_t)m) * 8 : 0);
     L.total = o;
     return L;
 }
@@ -76,6 +78,8 @@ Ptrs carve(const Layout &L, void *ws) {
     P.picked = (int *)(b + L.picked);
     P.tcnt = (int *)(b + L.tcnt);
     P.remain = (u64 *)(b + L.remain);
+    P.adone = (int *)(b + L.adone);
+    P.emat = (double *)(b + L.emat);
     return P;
 }
 
@@ -141,10 +145,13 @@ constexpr long long DOM_WAVES_PER_CU = 32;
 constexpr long long DOM_ROUNDS = 3;
 constexpr long long DOM_MAX_TILES = 3;
 
-static int auto_slice(int H, long long sum_W) {
+static int auto_slice(int H, long long sum_W, int m) {
     long long R = (long long)H * sum_W / ASSOC_WAVES;
     R = ((R + 15) / 16) * 16;
-    if (R < 32) R = 32;
+    // a reference costs a wave about 3m operations: above NARROW_M the
+    // slices stay short so that few points still spread over many waves
+    const long long lo = m > NARROW_M ? 16 : 32;
+    if (R < lo) R = lo;
     if (R > H) R = H;
     return (int)R;
 }
@@ -231,7 +238,7 @@ static void plan(std::vector<Spec> &spec, char *ws, int run, Plan &p) {
         I.W = L.W;
         I.Hp = L.Hp;
         I.G = spec[b].tile[0];  // 0: set per launch group below
-        I.R = spec[b].tile[1] > 0 ? spec[b].tile[1] : auto_slice(I.H, sum_W);
+        I.R = spec[b].tile[1] > 0 ? spec[b].tile[1] : auto_slice(I.H, sum_W, I.m);
         I.nslice = (I.H + I.R - 1) / I.R;
         tab[b] = I;
         pt[b + 1] = pt[b] + (int)((I.M + PT_ALIGN - 1) / PT_ALIGN * PT_ALIGN);
@@ -595,7 +602,7 @@ int nsga3_evolve_batched(const nsga3_evolve_slot *slots, int32_t B, void *ws, si
         const bool needs_old = q.mode != NSGA3_EVOLVE_INIT;
         if (q.mode < NSGA3_EVOLVE_GENERATION || q.mode > NSGA3_EVOLVE_INIT || q.reserved != 0 ||
             q.N < 1 || q.N > NSGA3_MAX_POINTS / 2 || q.d < 2 || q.d > NSGA3_MAX_DECISION ||
-            q.m < 2 || q.m > NSGA3_MAX_OBJECTIVES || q.generation < 0 ||
+            q.m < 2 || q.m > NSGA3_MAX_EVOLVE_OBJECTIVES || q.generation < 0 ||
             q.generation > 65535 || !q.X_new || !q.F_new || !q.A ||
             (needs_old && (!q.X_old || !q.F_old)) || !aligned(q.X_new, 4) ||
             !aligned(q.F_new, 4) || !aligned(q.A, 4))

@@ -13,9 +13,10 @@
 //
 // Kernels:
 //   k_assoc_list   (stage call) S_t list, key init, pi = dist = -1 outside S_t
-//   k_associate    the fused sweep
-//   k_assoc_final  pi and dist from the merged keys; in a whole selection
-//                  also the niche counts rho (fronts < l) and c (front l)
+//   k_associate    the fused sweep; the last slice of each block of list
+//                  entries writes pi and dist from the merged keys and, in a
+//                  whole selection, the niche counts rho (fronts < l) and c
+//                  (front l)
 #include "nsga3_internal.h"
 
 namespace nsga3 {
@@ -30,6 +31,7 @@ __global__ __launch_bounds__(256) void k_assoc_list(BatchView bv) {
         I.pi[t] = -1;
         I.dist[t] = -1.0f;
     }
+    if ((t & 63) == 0 && t < I.Mp) I.P.adone[t >> 6] = 0;
     const u64 bal = ballot(in);
     if (bal == 0) return;
     int base = 0;
@@ -57,6 +59,38 @@ __device__ __forceinline__ void assoc_ref(const float (&f)[MO], const NSGA3_RO f
         d2 = fmaf(r, r, d2);
     }
     if (d2 < best) { best = d2; bj = j; }
+}
+
+// Merges a wave's best (d^2, reference) of its slice into the keys of its
+// 64 list entries; the last slice of the block to finish reads the merged
+// keys: pi, dist and, in a whole selection, the niche counts rho (fronts < l)
+// and c (front l). Release: the minima are performed before the count; the
+// last wave acquires them all.
+__device__ __forceinline__ void assoc_merge(const BatchView &bv, CInst &I, int pb, int x, bool in,
+                                            bool any, float best, int bj) {
+    if (in && any) {
+        const u64 key = ((u64)__float_as_uint(best) << 32) | (unsigned)bj;
+        atomicMin(&I.P.akey[x], key);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    int done = 0;
+    if (lane_id() == 0)
+        done = __hip_atomic_fetch_add(&I.P.adone[pb], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (uniform(done) != I.nslice - 1) return;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    if (!in) return;
+    const u64 key = load_relaxed(&I.P.akey[x]);
+    int jm = (int)(unsigned)(key & 0xffffffffull);
+    if (jm < 0 || jm >= I.H) {
+        atomicOr(&I.P.ctrl->status, ST_INTERNAL);
+        jm = 0;
+    }
+    I.pi[x] = jm;
+    I.dist[x] = sqrtf(__uint_as_float((unsigned)(key >> 32)));
+    if (bv.run & RUN_NICHE) {
+        const int l = I.front_info[0];
+        atomicAdd(I.rank[x] < l ? &I.P.rho[jm] : &I.P.cnt[jm], 1);
+    }
 }
 
 // Work item = (block of 64 list entries, slice of R references) of one
@@ -107,31 +141,95 @@ __global__ __launch_bounds__(256) void k_associate(BatchView bv, int gs, int gn,
         assoc_ref<MO>(f, wn, Hp, j + 3, best, bj);
     }
     for (; j < h1; ++j) assoc_ref<MO>(f, wn, Hp, j, best, bj);
-    if (in && h0 < h1) {
-        const u64 key = ((u64)__float_as_uint(best) << 32) | (unsigned)bj;
-        atomicMin(&I.P.akey[x], key);
-    }
+    assoc_merge(bv, I, pb, x, in, h0 < h1, best, bj);
 }
 
-__global__ __launch_bounds__(256) void k_assoc_final(BatchView bv) {
-    const Local L = locate(bv.pt_pref, bv.B);
-    CInst &I = bv.tab[L.b];
-    Ctrl *ctrl = I.P.ctrl;
-    const int n = ctrl->list_count;
-    if (L.i >= n) return;
-    const int x = I.P.list[L.i];
-    const u64 key = I.P.akey[x];
-    int j = (int)(unsigned)(key & 0xffffffffull);
-    if (j < 0 || j >= I.H) {
-        atomicOr(&ctrl->status, ST_INTERNAL);
-        j = 0;
+// Association for m > NARROW_M: the same work items (64 list entries in the
+// lanes, a slice of references), with a point's objectives streamed in
+// chunks of AW_KC. References go in groups of AW_RG: one pass over the chunks
+// forms every projection p_j = f . w_j of the group, a second the squared
+// residuals sum_k (f_k - p_j w_jk)^2 (each sum by chunks, then over chunks).
+// Unit directions are rows (wn[j][k]), read through the scalar cache.
+constexpr int AW_KC = 16;
+constexpr int AW_RG = 32;
+
+__global__ __launch_bounds__(256) void k_associate_wide(BatchView bv, int gs, int gn,
+                                                         long long item0, long long n_items) {
+    const long long gitem = uniform(item0 + (long long)blockIdx.x * 4 + (threadIdx.x >> 6));
+    if (gitem >= item0 + n_items) return;
+    const int gi = uniform(find_range(bv.asc_pref + gs, gn, gitem));
+    CInst &I = bv.tab[bv.order[gs + gi]];
+    const long long item = gitem - bv.asc_pref[gs + gi];
+    const int n = I.P.ctrl->list_count;
+    const int pb = (int)(item / I.nslice);
+    const int sl = (int)(item % I.nslice);
+    if (pb * 64 >= n) return;
+    const int i = pb * 64 + lane_id();
+    const bool in = i < n;
+    const int x = in ? I.P.list[i] : I.P.list[pb * 64];
+    const bool fused = (bv.run & RUN_NORM) != 0;
+    const float *__restrict__ src = (fused ? I.F : I.Fn) + (size_t)x * I.m;
+    const NSGA3_RO float *wn = (const NSGA3_RO float *)I.P.wn;
+    const NSGA3_RO Ctrl *cc = (const NSGA3_RO Ctrl *)I.P.ctrl;
+    const int H = I.H, m = I.m;
+    const int h0 = sl * I.R;
+    const int h1 = min(h0 + I.R, H);
+    float best = INFINITY;
+    int bj = h0;
+    auto load_f = [&](int k0, float (&f)[AW_KC]) {
+#pragma unroll
+        for (int kk = 0; kk < AW_KC; ++kk) {
+            const int k = k0 + kk;
+            float v = 0.0f;
+            if (k < m) {
+                v = src[k];
+                if (fused) v = (v - cc->zf[k]) * cc->recip[k];
+            }
+            f[kk] = v;
+        }
+    };
+    for (int g0 = h0; g0 < h1; g0 += AW_RG) {
+        const int ng = min(AW_RG, h1 - g0);
+        float p[AW_RG], d2[AW_RG];
+#pragma unroll
+        for (int r = 0; r < AW_RG; ++r) p[r] = d2[r] = 0.0f;
+        for (int k0 = 0; k0 < m; k0 += AW_KC) {
+            float f[AW_KC];
+            load_f(k0, f);
+#pragma unroll
+            for (int r = 0; r < AW_RG; ++r) {
+                if (r >= ng) break;
+                const NSGA3_RO float *w = wn + (size_t)(g0 + r) * m + k0;
+                float acc = 0.0f;
+#pragma unroll
+                for (int kk = 0; kk < AW_KC; ++kk)
+                    if (k0 + kk < m) acc = fmaf(f[kk], w[kk], acc);
+                p[r] += acc;
+            }
+        }
+        for (int k0 = 0; k0 < m; k0 += AW_KC) {
+            float f[AW_KC];
+            load_f(k0, f);
+#pragma unroll
+            for (int r = 0; r < AW_RG; ++r) {
+                if (r >= ng) break;
+                const NSGA3_RO float *w = wn + (size_t)(g0 + r) * m + k0;
+                float acc = 0.0f;
+#pragma unroll
+                for (int kk = 0; kk < AW_KC; ++kk) {
+                    if (k0 + kk < m) {
+                        const float rr = fmaf(-p[r], w[kk], f[kk]);
+                        acc = fmaf(rr, rr, acc);
+                    }
+                }
+                d2[r] += acc;
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < AW_RG; ++r)
+            if (r < ng && d2[r] < best) { best = d2[r]; bj = g0 + r; }
     }
-    I.pi[x] = j;
-    I.dist[x] = sqrtf(__uint_as_float((unsigned)(key >> 32)));
-    if (bv.run & RUN_NICHE) {
-        const int l = I.front_info[0];
-        atomicAdd(I.rank[x] < l ? &I.P.rho[j] : &I.P.cnt[j], 1);
-    }
+    assoc_merge(bv, I, pb, x, in, h0 < h1, best, bj);
 }
 
 hipError_t launch_associate(const HostPlan &hp, const BatchView &bv, hipStream_t s) {
@@ -152,11 +250,13 @@ hipError_t launch_associate(const HostPlan &hp, const BatchView &bv, hipStream_t
             NSGA3_ASSOC_CASE(6) NSGA3_ASSOC_CASE(7) NSGA3_ASSOC_CASE(8) NSGA3_ASSOC_CASE(9)
             NSGA3_ASSOC_CASE(10) NSGA3_ASSOC_CASE(11) NSGA3_ASSOC_CASE(12) NSGA3_ASSOC_CASE(13)
             NSGA3_ASSOC_CASE(14) NSGA3_ASSOC_CASE(15) NSGA3_ASSOC_CASE(16)
-            default: return hipErrorInvalidValue;
+            default:
+                NSGA3_LAUNCH("associate", k_associate_wide, dim3(blocks), dim3(256), 0, s, bv, gs,
+                             gn, item0, n_items);
+                break;
         }
 #undef NSGA3_ASSOC_CASE
     }
-    NSGA3_LAUNCH("assoc_final", k_assoc_final, dim3(pblocks), dim3(256), 0, s, bv);
     return hipGetLastError();
 }
 

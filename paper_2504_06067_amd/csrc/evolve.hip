@@ -41,6 +41,7 @@ enum : unsigned {
 constexpr float EVO_ETA_C = 20.0f;
 constexpr float EVO_ETA_M = 20.0f;
 constexpr float EVO_XMAX = 0.99999994f;  // 1 - 2^-24
+constexpr int EVO_NARROW_D = 64;         // widest d of the row-per-thread kernel
 
 __device__ __forceinline__ u64 evo_hash(u64 seed, unsigned g, unsigned tag, unsigned i,
                                         unsigned j) {
@@ -73,7 +74,7 @@ struct EvoView {
 // Objectives of decision vector x (row of X_new just written by this thread).
 __device__ __forceinline__ void evo_objectives(const NSGA3_RO EvoSlot &S, const float *x, float *f) {
     const int d = S.d, m = S.m;
-    float y[NSGA3_MAX_OBJECTIVES];
+    float y[NSGA3_MAX_EVOLVE_OBJECTIVES];
     for (int k = 0; k < m; ++k) y[k] = 0.0f;
     for (int j = 0; j + 1 < d; ++j) {
         const float c = x[j] - 0.5f;
@@ -101,19 +102,19 @@ __device__ __forceinline__ float pm_delta(float u) {
     return u < 0.5f ? powf(2.0f * u, e) - 1.0f : 1.0f - powf(2.0f * (1.0f - u), e);
 }
 
-// One thread per output row of every slot.
+// One thread per output row of every slot with d <= EVO_NARROW_D.
 __global__ __launch_bounds__(256) void k_evolve(EvoView ev) {
     const int base = uniform((int)(blockIdx.x * blockDim.x));
     const int b = uniform(find_range(ev.row_pref, ev.B, base));
     const NSGA3_RO EvoSlot &S = ev.slot[b];
     const int r = base - ev.row_pref[b] + (int)threadIdx.x;
-    if (r >= S.rows) return;
+    if (r >= S.rows || S.d > EVO_NARROW_D) return;
     const int N = S.N, d = S.d, m = S.m;
     float *xo = S.X_new + (size_t)r * d;
     float *fo = S.F_new + (size_t)r * m;
     if (S.mode == NSGA3_EVOLVE_INIT) {
         for (int j = 0; j < d; ++j) xo[j] = evo_u01(evo_hash(S.seed, 0u, TAG_INIT, (unsigned)r, (unsigned)j));
-        float f[NSGA3_MAX_OBJECTIVES];
+        float f[NSGA3_MAX_EVOLVE_OBJECTIVES];
         evo_objectives(S, xo, f);
         for (int k = 0; k < m; ++k) fo[k] = f[k];
         return;
@@ -143,9 +144,88 @@ __global__ __launch_bounds__(256) void k_evolve(EvoView ev) {
             y = clamp01(y + pm_delta(evo_u01(evo_hash(S.seed, g, TAG_PM_U, (unsigned)i, (unsigned)j))));
         xo[j] = y;
     }
-    float f[NSGA3_MAX_OBJECTIVES];
+    float f[NSGA3_MAX_EVOLVE_OBJECTIVES];
     evo_objectives(S, xo, f);
     for (int k = 0; k < m; ++k) fo[k] = f[k];
+}
+
+// Float sum over the 64 lanes of a wave (butterfly; every lane gets it).
+__device__ __forceinline__ float wave_fsum(float v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Wide decision vectors (d > EVO_NARROW_D): one wave per output row, lanes
+// over the variables (coalesced rows), the same per-variable operations and
+// random draws as k_evolve; the objective map's sums over the variables are
+// per-lane partial sums reduced across the wave. Grid: 4 rows per block over
+// every slot's padded row range; rows of narrow slots leave at once.
+
+__global__ __launch_bounds__(256) void k_evolve_wide(EvoView ev) {
+    const int base = uniform((int)(blockIdx.x * 4));
+    const int b = uniform(find_range(ev.row_pref, ev.B, base));
+    const NSGA3_RO EvoSlot &S = ev.slot[b];
+    const int r = base - ev.row_pref[b] + (int)(threadIdx.x >> 6);
+    if (r >= S.rows || S.d <= EVO_NARROW_D) return;  // wave-uniform
+    const int lane = lane_id();
+    const int N = S.N, d = S.d, m = S.m;
+    float *xo = S.X_new + (size_t)r * d;
+    float *fo = S.F_new + (size_t)r * m;
+    if (S.mode != NSGA3_EVOLVE_INIT && r < N) {
+        const int src = S.sel ? S.sel[r] : r;
+        for (int j = lane; j < d; j += 64) xo[j] = S.X_old[(size_t)src * d + j];
+        if (lane < m) fo[lane] = S.F_old[(size_t)src * m + lane];
+        return;
+    }
+    const int i = r - N;
+    const unsigned k2 = (unsigned)(i >> 1);
+    const unsigned g = (unsigned)S.g;
+    int ra = 0, rb = 0;
+    if (S.mode != NSGA3_EVOLVE_INIT) {
+        const int pa = (int)(evo_hash(S.seed, g, TAG_PA, k2, 0u) % (u64)N);
+        const int pb = (int)(evo_hash(S.seed, g, TAG_PB, k2, 0u) % (u64)N);
+        ra = S.sel ? S.sel[pa] : pa;
+        rb = S.sel ? S.sel[pb] : pb;
+    }
+    const float pm_rate = 1.0f / (float)d;
+    float y[NSGA3_MAX_EVOLVE_OBJECTIVES];
+    for (int k = 0; k < m; ++k) y[k] = 0.0f;
+    float xlast = 0.0f;
+    for (int j = lane; j < d; j += 64) {
+        float x;
+        if (S.mode == NSGA3_EVOLVE_INIT) {
+            x = evo_u01(evo_hash(S.seed, 0u, TAG_INIT, (unsigned)r, (unsigned)j));
+        } else {
+            const float x1 = S.X_old[(size_t)ra * d + j];
+            const float x2 = S.X_old[(size_t)rb * d + j];
+            const float beta = sbx_beta(evo_u01(evo_hash(S.seed, g, TAG_SBX, k2, (unsigned)j)));
+            x = (i & 1) ? 0.5f * ((1.0f - beta) * x1 + (1.0f + beta) * x2)
+                        : 0.5f * ((1.0f + beta) * x1 + (1.0f - beta) * x2);
+            x = clamp01(x);
+            if (evo_u01(evo_hash(S.seed, g, TAG_PM_APPLY, (unsigned)i, (unsigned)j)) < pm_rate)
+                x = clamp01(x + pm_delta(evo_u01(evo_hash(S.seed, g, TAG_PM_U, (unsigned)i, (unsigned)j))));
+        }
+        xo[j] = x;
+        if (j + 1 < d) {
+            const float c = x - 0.5f;
+            for (int k = 0; k < m; ++k) y[k] = fmaf(S.A[k * (d - 1) + j], c, y[k]);
+        } else {
+            xlast = x;
+        }
+    }
+    float n2 = 0.0f;
+    for (int k = 0; k < m; ++k) {
+        y[k] = wave_fsum(y[k]);
+        n2 = fmaf(y[k], y[k], n2);
+    }
+    const float xl = __uint_as_float(
+        __builtin_amdgcn_readlane(__float_as_uint(xlast), (d - 1) & 63));
+    const float rad = 1.0f - 0.3f * logf(1.0f - xl);
+    const float inv = n2 > 0.0f ? 1.0f / sqrtf(n2) : 0.0f;
+    const float u0 = 1.0f / sqrtf((float)m);
+    for (int k = 0; k < m; ++k)
+        if (lane == k) fo[k] = (n2 > 0.0f ? fabsf(y[k]) * inv : u0) * rad;
 }
 
 size_t evolve_header_bytes(int B) {
@@ -184,7 +264,12 @@ hipError_t launch_evolve(const nsga3_evolve_slot *slots, int B, char *ws, hipStr
     ev.slot = (const NSGA3_RO EvoSlot *)ws;
     ev.row_pref = (const NSGA3_RO int *)(ws + off_pref);
     ev.B = B;
-    NSGA3_LAUNCH("evolve", k_evolve, dim3((unsigned)(pref[B] / 256)), dim3(256), 0, s, ev);
+    bool narrow = false, wide = false;
+    for (int b = 0; b < B; ++b) (slots[b].d > EVO_NARROW_D ? wide : narrow) = true;
+    if (narrow)
+        NSGA3_LAUNCH("evolve", k_evolve, dim3((unsigned)(pref[B] / 256)), dim3(256), 0, s, ev);
+    if (wide)
+        NSGA3_LAUNCH("evolve", k_evolve_wide, dim3((unsigned)(pref[B] / 4)), dim3(256), 0, s, ev);
     return hipGetLastError();
 }
 

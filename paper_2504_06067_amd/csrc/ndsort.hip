@@ -36,6 +36,12 @@ __global__ __launch_bounds__(256) void k_prep(BatchView bv, int npt) {
         CInst &I = bv.tab[L.b];
         const int j = L.i, M = I.M, m = I.m, Mp = I.Mp;
         bool bad = false;
+        // In a whole selection the ideal point is the least value of each
+        // objective over all points: a point that attains the least value
+        // and is not dominated among those that attain it is not dominated
+        // at all, so it is in front 0 and the least value over S_t is the
+        // same float. One atomic per wave and objective.
+        const bool ideal_here = (bv.run & RUN_ND) && (bv.run & RUN_NORM);
         if (j < Mp && (bv.run & RUN_ND)) {
             for (int k = 0; k < m; ++k) {
                 float v = INFINITY;
@@ -44,6 +50,10 @@ __global__ __launch_bounds__(256) void k_prep(BatchView bv, int npt) {
                     bad |= !isfinite(v);
                 }
                 I.P.ft[((size_t)(j >> 6) * m + k) * 64 + (j & 63)] = v;
+                if (ideal_here) {
+                    const unsigned lo = wave_min_u32(j < M ? f2ord(v) : 0xffffffffu);
+                    if (lane_id() == 0 && lo != 0xffffffffu) atomicMin(&I.P.ctrl->zmin_enc[k], lo);
+                }
             }
             I.P.nd[j] = 0;
             if (j < M) I.rank[j] = NSGA3_UNRANKED;
@@ -81,7 +91,13 @@ __global__ __launch_bounds__(256) void k_prep(BatchView bv, int npt) {
             }
             bad |= !(s > 0.0f);
             const float inv = bad ? 0.0f : 1.0f / sqrtf(s);
-            for (int k = 0; k < m; ++k) I.P.wn[(size_t)k * Hp + t] = I.Z[(size_t)j * m + k] * inv;
+            // structure of arrays for the specialized association kernels (a
+            // wave reads one objective of consecutive references), rows for
+            // the general one (a wave reads consecutive objectives of one)
+            for (int k = 0; k < m; ++k) {
+                const size_t at = m <= NARROW_M ? (size_t)k * Hp + t : (size_t)t * m + k;
+                I.P.wn[at] = I.Z[(size_t)j * m + k] * inv;
+            }
         }
         if (t < H && (bv.run & RUN_NICHE)) {
             I.P.rho[t] = 0;
@@ -195,7 +211,8 @@ __device__ __forceinline__ void dom_tile(std::integer_sequence<int, Gs...>,
 // scalar cache.
 template <int MO>
 __global__ __launch_bounds__(256) void k_dominance(BatchView bv, int gs, int gn,
-                                                    long long item0, long long n_items) {
+                                                    long long item0, long long n_items,
+                                                    int counts) {
     const int lane = lane_id();
     const long long gitem = uniform(item0 + (long long)blockIdx.x * 4 + (threadIdx.x >> 6));
     if (gitem >= item0 + n_items) return;
@@ -234,13 +251,105 @@ __global__ __launch_bounds__(256) void k_dominance(BatchView bv, int gs, int gn,
                 const u64 B = ((u64)b_hi << 32) | b_lo;
                 mask[(size_t)jb * Mp + (size_t)ib * 64 + lane] = B;
                 const int c = __popcll(B);
-                if (c) atomicAdd(&nd[ib * 64 + lane], c);
+                if (counts && c) atomicAdd(&nd[ib * 64 + lane], c);
             }
         }
-        if (cnt_j) atomicAdd(&nd[jglob], cnt_j);
+        if (counts && cnt_j) atomicAdd(&nd[jglob], cnt_j);
         t = tri(jb) + ib1;
         ++jb;
         ib = 0;
+    }
+}
+
+// Dominance for m > NARROW_M (the many-objective regime): the objectives of a
+// point no longer fit in registers, so each tile runs over chunks of DW_KC
+// objectives. Per chunk, the wave stages the column block's values in LDS
+// (its own region) and keeps the row values in registers; per column point i
+// it ORs the ballots lt_i = {j : f_i < f_j in some objective} and gt_i =
+// {j : f_i > f_j in some objective} into per-wave LDS words. A column point
+// whose every row point is already incomparable (lt_i and gt_i both set) is
+// skipped, and the tile ends once every column point is, which at large m
+// comes after a few objectives for most pairs. The words are those of
+// k_dominance: bit i of row word j is i -> j (j in lt_i \ gt_i), and column
+// point i's word from this row block is gt_i \ lt_i. Work items, tiles and
+// the fused counts are as in k_dominance.
+constexpr int DW_KC = 32;
+
+__global__ __launch_bounds__(256) void k_dominance_wide(BatchView bv, int gs, int gn,
+                                                         long long item0, long long n_items,
+                                                         int counts) {
+    __shared__ float s_col[4][64][DW_KC + 1];  // padded rows: conflict-free staging
+    __shared__ u64 s_lt[4][64], s_gt[4][64];
+    const int lane = lane_id();
+    const int wv = threadIdx.x >> 6;
+    const long long gitem = uniform(item0 + (long long)blockIdx.x * 4 + wv);
+    if (gitem >= item0 + n_items) return;
+    const int gi = uniform(find_range(bv.dom_pref + gs, gn, gitem));
+    CInst &I = bv.tab[bv.order[gs + gi]];
+    const long long item = gitem - bv.dom_pref[gs + gi];
+    const int W = I.W, Mp = I.Mp, m = I.m, M = I.M;
+    const long long G = I.G, T = tri(W);
+    const float *__restrict__ ft = I.P.ft;
+    u64 *__restrict__ mask = I.P.mask;
+    int *__restrict__ nd = I.P.nd;
+    long long t = item * G;
+    const long long t_end = t + G < T ? t + G : T;
+    while (t < t_end) {
+        const int jb = uniform(row_of(t));
+        const int ib = (int)(t - tri(jb));
+        const u64 rowvalid = M - jb * 64 >= 64 ? ~0ull : ((1ull << (M - jb * 64)) - 1);
+        const int ncol = M - ib * 64 >= 64 ? 64 : M - ib * 64;  // real column points
+        s_lt[wv][lane] = 0ull;
+        s_gt[wv][lane] = 0ull;
+        for (int k0 = 0; k0 < m; k0 += DW_KC) {
+            const int kc = m - k0 < DW_KC ? m - k0 : DW_KC;
+            float fj[DW_KC];
+#pragma unroll
+            for (int kk = 0; kk < DW_KC; ++kk) {
+                fj[kk] = kk < kc ? ft[((size_t)jb * m + k0 + kk) * 64 + lane] : 0.0f;
+                if (kk < kc) s_col[wv][lane][kk] = ft[((size_t)ib * m + k0 + kk) * 64 + lane];
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            int open = 0;
+            for (int i = 0; i < ncol; ++i) {
+                u64 lt = uniform(s_lt[wv][i]), gt = uniform(s_gt[wv][i]);
+                if (((lt & gt) | ~rowvalid) == ~0ull) continue;
+                for (int kk = 0; kk < kc; ++kk) {
+                    const float x = s_col[wv][i][kk];
+                    lt |= ballot(x < fj[kk]);
+                    gt |= ballot(x > fj[kk]);
+                }
+                if (lane == 0) {
+                    s_lt[wv][i] = lt;
+                    s_gt[wv][i] = gt;
+                }
+                open += ((lt & gt) | ~rowvalid) != ~0ull;
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            if (uniform(open) == 0) break;  // every pair of the tile is incomparable
+        }
+        // row word of lane j: bit i = i -> j
+        u64 A = 0;
+        for (int i = 0; i < ncol; ++i) {
+            const u64 d = uniform(s_lt[wv][i]) & ~uniform(s_gt[wv][i]);
+            A |= ((d >> lane) & 1ull) << i;
+        }
+        mask[(size_t)ib * Mp + (size_t)jb * 64 + lane] = A;
+        const int cnt_j = __popcll(A);
+        if (counts && cnt_j) atomicAdd(&nd[jb * 64 + lane], cnt_j);
+        if (ib != jb) {
+            // column point i = lane: its dominators in row block jb
+            const u64 B = lane < ncol ? (s_gt[wv][lane] & ~s_lt[wv][lane] & rowvalid) : 0ull;
+            mask[(size_t)jb * Mp + (size_t)ib * 64 + lane] = B;
+            const int c = __popcll(B);
+            if (counts && c) atomicAdd(&nd[ib * 64 + lane], c);
+        }
+        __builtin_amdgcn_wave_barrier();  // LDS words are reused by the next tile
+        ++t;
     }
 }
 
@@ -506,6 +615,37 @@ __device__ void peel_pair(CInst &I, int k, int c0, int c1, PeelShared &sh, const
     lds_barrier();  // the shared partial sums are free again
 }
 
+// Dominator counts of chunk c (popcounts over its whole column, streamed
+// once) into the counts in global memory, for a chunk beyond the cache slots
+// of a peel whose dominance launch did not count. All waves take part.
+__device__ void count_streamed(CInst &I, int c, PeelShared &sh) {
+    const int lane = lane_id();
+    const int wv = uniform((int)(threadIdx.x >> 6));
+    const int W = I.W;
+    const size_t Mp = (size_t)I.Mp;
+    const u64 *__restrict__ src = I.P.mask + (size_t)c * 64 + lane;
+    int acc = 0;
+    for (int w0 = wv; w0 < W; w0 += PEEL_WAVES * 4) {
+        u64 x[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int w = w0 + q * PEEL_WAVES;
+            x[q] = w < W ? src[(size_t)w * Mp] : 0ull;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc += __popcll(x[q]);
+    }
+    sh.part[0][wv][lane] = acc;
+    lds_barrier();
+    if (wv == 0) {
+        int cnt = 0;
+#pragma unroll
+        for (int v = 0; v < PEEL_WAVES; ++v) cnt += sh.part[0][v][lane];
+        I.P.nd[c * 64 + lane] = cnt;
+    }
+    lds_barrier();  // the shared partial sums are free again
+}
+
 // A chunk whose column is streamed.
 template <int BATCH>
 __device__ __forceinline__ void peel_chunk(CInst &I, int k, int c, int own, PeelShared &sh) {
@@ -525,14 +665,15 @@ __global__ __launch_bounds__(64 * PEEL_WAVES) void k_peel(BatchView bv, int nchu
     const int wv = uniform((int)(threadIdx.x >> 6));
     const u64 one = lane == 0 ? 1ull : 0ull;
 
-    // front 0: claim and rank chunks until all are claimed. Ticket shard s
-    // hands out chunks s, s + TICKET_SHARDS, ...; a workgroup starts at its
-    // own shard and moves on when one runs dry (the shards spread the claims
-    // over many addresses)
+    // Front 0: claim chunks until all are claimed. Ticket shard s hands out
+    // chunks s, s + TICKET_SHARDS, ...; a workgroup starts at its own shard
+    // and moves on when one runs dry (the shards spread the claims over many
+    // addresses). Returns the claimed chunk (uniform), or nchunk or more
+    // when none is left.
     int nown = 0;
     const int home = (int)(blockIdx.x % TICKET_SHARDS);
     bool home_dry = false;
-    for (;;) {
+    auto claim = [&]() -> u64 {
         if (wv == 0) {
             u64 t = ~0ull;
             for (;;) {
@@ -542,8 +683,8 @@ __global__ __launch_bounds__(64 * PEEL_WAVES) void k_peel(BatchView bv, int nchu
                     if (g < (u64)nchunk) { t = g; break; }
                     home_dry = true;
                 }
-                // look at every shard at once; claim from one that has chunks left
-                // (starting after the home shard), or stop when none has
+                // look at every shard at once; claim from one that has chunks
+                // left (starting after the home shard), or stop when none has
                 const u64 n_l = lane < TICKET_SHARDS ? load_relaxed(&bv.ticket[lane * TICKET_STRIDE]) : 0ull;
                 const u64 avail = ballot(lane < TICKET_SHARDS &&
                                          (u64)lane + (u64)TICKET_SHARDS * n_l < (u64)nchunk);
@@ -561,30 +702,80 @@ __global__ __launch_bounds__(64 * PEEL_WAVES) void k_peel(BatchView bv, int nchu
         lds_barrier();
         const u64 t = uniform(sh.val);
         lds_barrier();
-        if (t >= (u64)nchunk) break;
-        const int b = uniform(find_range(bv.chunk_pref, bv.B, (int)t));
-        const int c = (int)t - bv.chunk_pref[b];
-        peel_chunk<BATCH>(bv.tab[b], 0, c, nown, sh);
+        return t;
+    };
+    // Records claimed chunk t as owned chunk nown (wave 0 writes, the
+    // caller's next barrier publishes it).
+    auto own = [&](u64 t, int &b, int &c) {
+        b = uniform(find_range(bv.chunk_pref, bv.B, (int)t));
+        c = (int)t - bv.chunk_pref[b];
         if (wv == 0) {
-            // counts of a chunk with a cache slot move to LDS
-            if (Q > 0 && nown < PEEL_CACHE_SLOTS) sh.cleft[nown][lane] = bv.tab[b].P.nd[c * 64 + lane];
             sh.own_b[nown] = b;
             sh.own_c[nown] = c;
             sh.own_cum[1][nown] = 0;
         }
+    };
+    // Streamed columns: front 0 of each chunk at its claim, from the counts
+    // fused into the dominance kernel. Cached columns: up to PEEL_CACHE_SLOTS
+    // claims, then front 0 of those from counts over their loaded columns;
+    // then, while chunks are left, further claims streamed as above but
+    // counting over their column first. Every running workgroup claims until
+    // none is left, so every chunk has a running owner.
+    bool dry = false;
+    while (nown < (Q > 0 ? PEEL_CACHE_SLOTS : PEEL_OWN_CAP)) {
+        const u64 t = claim();
+        if (t >= (u64)nchunk) { dry = true; break; }
+        int b, c;
+        own(t, b, c);
+        if (Q == 0) peel_chunk<BATCH>(bv.tab[b], 0, c, nown, sh);
         ++nown;
-        if (nown == PEEL_OWN_CAP) break;
     }
     lds_barrier();
+    u64 col0[Q > 0 ? Q : 1], col1[Q > 0 ? Q : 1];
+    if constexpr (Q > 0) {
+        if (nown > 0) {
+            const int b0 = uniform(sh.own_b[0]), c0 = uniform(sh.own_c[0]);
+            const int b1 = nown > 1 ? uniform(sh.own_b[1]) : b0;
+            const int c1 = nown > 1 ? uniform(sh.own_c[1]) : c0;
+            load_column<Q>(bv.tab[b0], c0, col0);
+            if (nown > 1) load_column<Q>(bv.tab[b1], c1, col1);
+            int a0 = 0, a1 = 0;
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                a0 += __popcll(col0[q]);
+                a1 += nown > 1 ? __popcll(col1[q]) : 0;
+            }
+            sh.part[0][wv][lane] = a0;
+            sh.part[1][wv][lane] = a1;
+            lds_barrier();
+            if (wv < nown) {  // waves 0 and 1: slots 0 and 1
+                const int slot = wv;
+                CInst &I = bv.tab[slot ? b1 : b0];
+                const int c = slot ? c1 : c0;
+                int cnt = 0;
+#pragma unroll
+                for (int v = 0; v < PEEL_WAVES; ++v) cnt += sh.part[slot][v][lane];
+                sh.cleft[slot][lane] = cnt;
+                const int valid = I.M - c * 64;
+                const u64 aw = valid >= 64 ? ~0ull : ((1ull << valid) - 1);
+                publish(I, 0, c, slot, aw, aw & ballot(cnt == 0), sh);
+            }
+            lds_barrier();  // the shared partial sums are free again
+        }
+        while (!dry && nown < PEEL_OWN_CAP) {
+            const u64 t = claim();
+            if (t >= (u64)nchunk) break;
+            int b, c;
+            own(t, b, c);
+            count_streamed(bv.tab[b], c, sh);
+            peel_chunk<BATCH>(bv.tab[b], 0, c, nown, sh);
+            ++nown;
+        }
+        lds_barrier();
+    }
     // a workgroup without chunks has nothing left to do; the owners of the
     // chunks report the front fill
     if (nown == 0) return;
-    // the cached columns load while the other chunks of front 0 finish
-    u64 col0[Q > 0 ? Q : 1], col1[Q > 0 ? Q : 1];
-    if constexpr (Q > 0) {
-        load_column<Q>(bv.tab[uniform(sh.own_b[0])], uniform(sh.own_c[0]), col0);
-        if (nown > 1) load_column<Q>(bv.tab[uniform(sh.own_b[1])], uniform(sh.own_c[1]), col1);
-    }
 
     for (int k = 1;; ++k) {
         const int cur = k & 1, nxt = cur ^ 1;
@@ -649,27 +840,12 @@ hipError_t launch_prepare(const HostPlan &hp, const BatchView &bv, bool init_don
 }
 
 hipError_t launch_nd_sort(const HostPlan &hp, const BatchView &bv, hipStream_t s) {
-    for (int g = 0; g < hp.ngroups; ++g) {
-        const int gs = hp.grp_start[g], gn = hp.grp_start[g + 1] - gs;
-        const long long item0 = hp.grp_dom[g], n_items = hp.grp_dom[g + 1] - item0;
-        const unsigned blocks = (unsigned)((n_items + 3) / 4);
-#define NSGA3_DOM_CASE(MO)                                                                       \
-    case MO:                                                                                     \
-        NSGA3_LAUNCH("dominance", k_dominance<MO>, dim3(blocks), dim3(256), 0, s, bv, gs, gn,   \
-                     item0, n_items);                                                            \
-        break;
-        switch (hp.grp_m[g]) {
-            NSGA3_DOM_CASE(2) NSGA3_DOM_CASE(3) NSGA3_DOM_CASE(4) NSGA3_DOM_CASE(5)
-            NSGA3_DOM_CASE(6) NSGA3_DOM_CASE(7) NSGA3_DOM_CASE(8) NSGA3_DOM_CASE(9)
-            NSGA3_DOM_CASE(10) NSGA3_DOM_CASE(11) NSGA3_DOM_CASE(12) NSGA3_DOM_CASE(13)
-            NSGA3_DOM_CASE(14) NSGA3_DOM_CASE(15) NSGA3_DOM_CASE(16)
-            default: return hipErrorInvalidValue;
-        }
-#undef NSGA3_DOM_CASE
-    }
     // Columns stay in registers when every instance's column fits a cache
     // and two cached chunks per compute unit hold all chunks (one workgroup
     // per compute unit at that register use); otherwise they are streamed.
+    // A peel with cached columns counts dominators from them; a streamed one
+    // takes the counts fused into the dominance kernel (its front 0 then
+    // needs no pass over the matrix).
     const int cus = device_info().cus;
     int q = 0;
     if (hp.nchunk <= PEEL_CACHE_SLOTS * cus) {
@@ -678,6 +854,27 @@ hipError_t launch_nd_sort(const HostPlan &hp, const BatchView &bv, hipStream_t s
                 q = c;
                 break;
             }
+    }
+    for (int g = 0; g < hp.ngroups; ++g) {
+        const int gs = hp.grp_start[g], gn = hp.grp_start[g + 1] - gs;
+        const long long item0 = hp.grp_dom[g], n_items = hp.grp_dom[g + 1] - item0;
+        const unsigned blocks = (unsigned)((n_items + 3) / 4);
+#define NSGA3_DOM_CASE(MO)                                                                       \
+    case MO:                                                                                     \
+        NSGA3_LAUNCH("dominance", k_dominance<MO>, dim3(blocks), dim3(256), 0, s, bv, gs, gn,   \
+                     item0, n_items, q == 0 ? 1 : 0);                                            \
+        break;
+        switch (hp.grp_m[g]) {
+            NSGA3_DOM_CASE(2) NSGA3_DOM_CASE(3) NSGA3_DOM_CASE(4) NSGA3_DOM_CASE(5)
+            NSGA3_DOM_CASE(6) NSGA3_DOM_CASE(7) NSGA3_DOM_CASE(8) NSGA3_DOM_CASE(9)
+            NSGA3_DOM_CASE(10) NSGA3_DOM_CASE(11) NSGA3_DOM_CASE(12) NSGA3_DOM_CASE(13)
+            NSGA3_DOM_CASE(14) NSGA3_DOM_CASE(15) NSGA3_DOM_CASE(16)
+            default:
+                NSGA3_LAUNCH("dominance", k_dominance_wide, dim3(blocks), dim3(256), 0, s, bv, gs,
+                             gn, item0, n_items, q == 0 ? 1 : 0);
+                break;
+        }
+#undef NSGA3_DOM_CASE
     }
     const int cap = q ? cus : 3 * cus;
     const int peel_blocks = hp.nchunk < cap ? hp.nchunk : cap;

@@ -72,6 +72,7 @@ __device__ __forceinline__ long long block_sum_ll(long long v, long long *red) {
 // at a time; larger H takes several groups of rows.
 constexpr int PLAN_PER = 12;
 constexpr int PLAN_WAVES = PLAN_THREADS / 64;
+constexpr int PLAN_TCAP = 2048;  // members of T whose keys are gathered in LDS
 
 __device__ __forceinline__ long long block_max_ll(long long v, long long *red) {
 #pragma unroll
@@ -102,6 +103,9 @@ __global__ __launch_bounds__(PLAN_THREADS) void k_niche_plan(BatchView bv) {
     __shared__ int s_sel[4];
     __shared__ int s_lev[4];  // L*, |T|, P(L*), L* beyond the level window
     __shared__ int wt2[PLAN_WAVES];
+    __shared__ int t_ref[PLAN_TCAP];   // listed members of T: reference, niche count, key
+    __shared__ int t_rho[PLAN_TCAP];
+    __shared__ u64 t_key[PLAN_TCAP];
     const int tid = threadIdx.x;
     const int wv = uniform((int)(threadIdx.x >> 6));
     const int lane = lane_id();
@@ -266,6 +270,38 @@ __global__ __launch_bounds__(PLAN_THREADS) void k_niche_plan(BatchView bv) {
     // bijection).
     u64 prefix = 0;
     const bool every = r >= tsize;  // r == |T|: every key of T qualifies
+    // Up to PLAN_TCAP members of T are gathered into LDS first, so that each
+    // key is hashed once, by one thread (a key costs several 64-bit
+    // multiplies, and T is a small, scattered subset of the references).
+    const bool listed = r > 0 && r < tsize && tsize <= PLAN_TCAP;
+    int ntk = 0;
+    if (listed) {
+        if (tid == 0) s_sel[3] = 0;
+        lds_barrier();
+        for (int g = 0; g < groups; ++g) {
+            if (groups > 1) load_group(g);
+#pragma unroll
+            for (int q = 0; q < PLAN_PER; ++q) {
+                const int j = (g * PLAN_PER + q) * PLAN_THREADS + tid;
+                const bool in_t = j < H && cc[q] > 0 && rc[q] <= Ls && Ls < rc[q] + cc[q];
+                const u64 bal = ballot(in_t);
+                if (bal == 0) continue;  // wave-uniform
+                int base = 0;
+                if (lane == 0) base = atomicAdd(&s_sel[3], __popcll(bal));
+                base = uniform(base);
+                if (in_t) {
+                    t_ref[base + mbcnt(bal)] = j;
+                    t_rho[base + mbcnt(bal)] = rc[q];
+                }
+            }
+        }
+        if (groups > 1) load_group(0);
+        lds_barrier();
+        ntk = uniform(s_sel[3]);
+        for (int e = tid; e < ntk; e += PLAN_THREADS)
+            t_key[e] = tie_key(seed, 1u, (unsigned)t_ref[e], (unsigned)Ls);
+        lds_barrier();
+    }
     if (r > 0 && r < tsize) {
         // keys of the owned members of T (group 0 when it is the only one)
         u64 kc[PLAN_PER];
@@ -273,12 +309,17 @@ __global__ __launch_bounds__(PLAN_THREADS) void k_niche_plan(BatchView bv) {
         for (int q = 0; q < PLAN_PER; ++q) {
             const int j = q * PLAN_THREADS + tid;
             kc[q] = 0ull;
-            if (groups == 1 && j < H && cc[q] > 0 && rc[q] <= Ls && Ls < rc[q] + cc[q])
+            if (!listed && groups == 1 && j < H && cc[q] > 0 && rc[q] <= Ls && Ls < rc[q] + cc[q])
                 kc[q] = tie_key(seed, 1u, (unsigned)j, (unsigned)Ls);
         }
         // calls BODY with `key` for every key of T owned by this thread
 #define PLAN_KEYS(BODY)                                                                       \
-    if (groups == 1) {                                                                        \
+    if (listed) {                                                                             \
+        for (int e = tid; e < ntk; e += PLAN_THREADS) {                                       \
+            const u64 key = t_key[e];                                                         \
+            BODY                                                                              \
+        }                                                                                     \
+    } else if (groups == 1) {                                                                 \
         _Pragma("unroll") for (int q = 0; q < PLAN_PER; ++q) {                                \
             const int j = q * PLAN_THREADS + tid;                                             \
             if (j < H && cc[q] > 0 && rc[q] <= Ls && Ls < rc[q] + cc[q]) {                    \
@@ -365,14 +406,19 @@ __global__ __launch_bounds__(PLAN_THREADS) void k_niche_plan(BatchView bv) {
         }
 #undef PLAN_KEYS
     }
+    // per-reference pick counts: up to level L*, plus one at L* for the r
+    // least keys of T (members of a listed T are written from the list)
     PLAN_FOR({
-        int t = (int)min((long long)cj, max(0ll, (long long)Ls - rj));
-        if (r > 0 && cj > 0 && rj <= Ls && Ls < rj + cj &&
-            (every || tie_key(seed, 1u, (unsigned)j, (unsigned)Ls) <= prefix))
-            t += 1;
-        tpick[j] = t;
+        const bool in_t = r > 0 && cj > 0 && rj <= Ls && Ls < rj + cj;
+        if (!(listed && in_t)) {
+            int t = (int)min((long long)cj, max(0ll, (long long)Ls - rj));
+            if (in_t && (every || tie_key(seed, 1u, (unsigned)j, (unsigned)Ls) <= prefix)) t += 1;
+            tpick[j] = t;
+        }
     })
 #undef PLAN_FOR
+    for (int e = tid; e < ntk; e += PLAN_THREADS)
+        tpick[t_ref[e]] = Ls - t_rho[e] + (t_key[e] <= prefix ? 1 : 0);
     if (wv == 0) {
         ctrl->all_pick = 0;
         ctrl->lstar = Ls;

@@ -38,6 +38,10 @@ enum : int {
     RUN_SELECT = 15,
 };
 
+// Objective counts up to NARROW_M run kernels specialized per m (values of
+// one point in registers); larger m runs general kernels.
+constexpr int NARROW_M = 16;
+
 // Device-resident control block at the start of every instance's workspace.
 struct Ctrl {
     int status;
@@ -72,7 +76,7 @@ constexpr int TICKET_STRIDE = 32;   // u64 words between them (256 bytes)
 struct Layout {
     int M, m, H, N, Mp, W, Hp;
     size_t ctrl, ft, nd, mask, ring, list, fn, rank, pi, dist, akey, wn,
-        rho, cnt, off, fill, tpick, members, picked, tcnt, remain, total;
+        rho, cnt, off, fill, tpick, members, picked, tcnt, remain, adone, emat, total;
 };
 
 Layout make_layout(int M, int m, int H, int N);
@@ -92,6 +96,8 @@ struct Ptrs {
     int *rho, *cnt, *off, *fill, *tpick, *members, *picked;
     int *tcnt;          // selected points per compaction tile
     u64 *remain;
+    int *adone;         // association: slices merged per block of 64 list entries
+    double *emat;       // m > NARROW_M: the intercept system [m][m], rhs, column maxima, b
 };
 
 Ptrs carve(const Layout &L, void *ws);
@@ -354,10 +360,10 @@ __device__ __forceinline__ void init_instance(Ctrl *ctrl, int *front_info, int n
             front_info[3] = 0;
         }
     }
-    if (t < NSGA3_MAX_OBJECTIVES) {
-        ctrl->zmin_enc[t] = 0xffffffffu;
-        ctrl->fmax_enc[t] = 0u;
-        ctrl->ext_key[t] = ~0ull;
+    for (int k = t; k < NSGA3_MAX_OBJECTIVES; k += 256) {
+        ctrl->zmin_enc[k] = 0xffffffffu;
+        ctrl->fmax_enc[k] = 0u;
+        ctrl->ext_key[k] = ~0ull;
     }
 }
 

@@ -8,7 +8,9 @@ offspring step (mating, SBX, polynomial mutation and the objective map:
 
 The server admits requests in arrival order as soon as they have arrived and
 their memory fits in the HBM budget (a first-fit pool carved from one device
-allocation; a request that does not fit waits, and so does every later one).
+allocation). A request that does not fit waits; later requests that fit may
+pass it, up to a bounded number of times, after which it holds the queue
+until it is admitted.
 Every tick advances all resident runs by one generation with one batched
 launch sequence, so runs that arrive while others are on the GPU join the
 next tick and share its launches. A run leaves after its last generation;
@@ -182,6 +184,39 @@ class Lane:
         self.hdr = nsga3.Workspace(device)
 
 
+def admit_arrived(queue, now, try_admit, passed, max_bypass):
+    """One admission pass over the queue (sorted by arrival): the arrived
+    requests in order, each through try_admit(q) (True: admitted, False: does
+    not fit now, None: can never fit, dropped). A request that does not fit
+    is passed by later ones that fit, at most `max_bypass` times (counted in
+    `passed`, rid -> admissions ahead of it); then it holds every later
+    request until it is admitted, so a large request cannot starve. Removes
+    the admitted and dropped requests from `queue`; returns how many
+    admissions passed a waiting request."""
+    i = bypasses = 0
+    while i < len(queue) and queue[i]["arrival"] <= now:
+        q = queue[i]
+        r = try_admit(q)
+        if r is None:
+            del queue[i]
+            continue
+        if not r:
+            if passed.get(q["rid"], 0) >= max_bypass:
+                break
+            i += 1
+            continue
+        held = False
+        for k in range(i):
+            rid = queue[k]["rid"]
+            passed[rid] = passed.get(rid, 0) + 1
+            held |= passed[rid] >= max_bypass
+        del queue[i]
+        bypasses += i > 0
+        if held:
+            break
+    return bypasses
+
+
 class Server:
     """Runs a request trace.
 
@@ -192,9 +227,10 @@ class Server:
     mode "plain": one request at a time, plain per-instance calls, one stream."""
 
     def __init__(self, device="cuda:0", budget=DEFAULT_BUDGET, mode="batched",
-                 max_batch=nsga3.MAX_BATCH, depth=2, lanes=(8192, 32768)):
+                 max_batch=nsga3.MAX_BATCH, depth=2, lanes=(8192, 32768), max_bypass=8):
         if mode not in ("batched", "plain"):
             raise ValueError(mode)
+        self.max_bypass = max_bypass
         self.device = torch.device(device)
         self.mode = mode
         self.plain = mode == "plain"
@@ -286,6 +322,8 @@ class Server:
         torch.cuda.synchronize(dev)
         queue = collections.deque(sorted(trace, key=lambda q: (q["arrival"], q["rid"])))
         results, pending = {}, []
+        passed = {}      # rid -> later requests admitted ahead of it
+        bypasses = 0     # admissions that passed a waiting request
         t_ev = torch.cuda.Event(enable_timing=True)
         t_ev.record(torch.cuda.current_stream(dev))
         t0 = time.perf_counter()
@@ -317,27 +355,25 @@ class Server:
         def busy():
             return any(lane.active for lane in self.lanes)
 
+        def try_admit(q):
+            # True: admitted; False: does not fit now; None: never fits
+            lane = self._lane_of(q["M"])
+            lay, nb = slot_layout(q["M"], q["m"], len(q["Z"]), q["d"], self.plain)
+            if nb > self.pool.size:
+                results[q["rid"]] = dict(status=nsga3.EWORKSPACE, latency_s=None, done_s=None)
+                return None
+            off = self.pool.alloc(nb) if len(lane.active) < lane.max_active else None
+            if off is None:
+                return False
+            with torch.cuda.stream(lane.stream):
+                run = Run(q, self.pool, off, lay)
+            run.nbytes = nb
+            lane.newly.append(run)
+            lane.active.append(run)
+            return True
+
         while queue or busy() or pending:
-            # admission: arrived requests, in order, while memory and slots allow
-            while queue and queue[0]["arrival"] <= now():
-                q = queue[0]
-                lane = self._lane_of(q["M"])
-                if len(lane.active) >= lane.max_active:
-                    break
-                lay, nb = slot_layout(q["M"], q["m"], len(q["Z"]), q["d"], self.plain)
-                if nb > self.pool.size:
-                    queue.popleft()
-                    results[q["rid"]] = dict(status=nsga3.EWORKSPACE, latency_s=None, done_s=None)
-                    continue
-                off = self.pool.alloc(nb)
-                if off is None:
-                    break
-                queue.popleft()
-                with torch.cuda.stream(lane.stream):
-                    run = Run(q, self.pool, off, lay)
-                run.nbytes = nb
-                lane.newly.append(run)
-                lane.active.append(run)
+            bypasses += admit_arrived(queue, now(), try_admit, passed, self.max_bypass)
             n_active = sum(len(lane.active) for lane in self.lanes)
             peak_active = max(peak_active, n_active)
             peak_bytes = max(peak_bytes, self.pool.used())
@@ -364,5 +400,5 @@ class Server:
         makespan = max((r["done_s"] for r in results.values() if r.get("done_s") is not None),
                        default=0.0)
         results[None] = dict(ticks=ticks, makespan_s=makespan, peak_active=peak_active,
-                             peak_pool_bytes=peak_bytes)
+                             peak_pool_bytes=peak_bytes, bypasses=bypasses)
         return results

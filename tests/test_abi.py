@@ -44,7 +44,8 @@ def test_workspace_bytes(lib):
     ws = lib.nsga3_workspace_bytes
     assert ws(1, 3, 10, 1) == 0          # M < 2
     assert ws(100, 1, 10, 50) == 0       # m < 2
-    assert ws(100, 17, 10, 50) == 0      # m > 16
+    assert ws(100, 513, 10, 50) == 0     # m > 512
+    assert ws(100, 512, 10, 50) > 0      # m = 512: the general kernels
     assert ws(100, 3, 0, 50) == 0        # H < 1
     assert ws(100, 3, 10, 101) == 0      # N > M
     assert ws(2**20 + 1, 3, 10, 5) == 0  # M too large
@@ -68,7 +69,7 @@ def test_invalid_arguments_enqueue_nothing(lib):
     assert lib.nsga3_select(fake, 10, 3, fake, 5, 5, 0, fake, None, None, None, P(4100), 1 << 30,
                             None) == -1
     # m out of range
-    assert lib.nsga3_select(fake, 10, 17, fake, 5, 5, 0, fake, None, None, None, fake, 1 << 30,
+    assert lib.nsga3_select(fake, 10, 513, fake, 5, 5, 0, fake, None, None, None, fake, 1 << 30,
                             None) == -1
 
 

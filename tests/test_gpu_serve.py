@@ -23,7 +23,8 @@ def _buffers(dev, rows, d, m):
     return (torch.full((rows * d,), -1.0, device=dev), torch.full((rows * m,), -1.0, device=dev))
 
 
-@pytest.mark.parametrize("N,d,m", [(1, 2, 2), (37, 12, 3), (300, 12, 15), (257, 64, 16)])
+@pytest.mark.parametrize("N,d,m", [(1, 2, 2), (37, 12, 3), (300, 12, 15), (257, 64, 16),
+                                   (5, 65, 2), (7, 500, 6), (3, 1024, 16)])
 def test_init_population_exact(N, d, m):
     dev = device()
     A = np.random.default_rng(N).standard_normal((m, d - 1)).astype(np.float32)
@@ -36,7 +37,8 @@ def test_init_population_exact(N, d, m):
 
 
 @pytest.mark.parametrize("N,d,m,g", [(2, 12, 3, 1), (41, 12, 5, 7), (500, 12, 10, 50),
-                                     (64, 3, 2, 65535)])
+                                     (64, 3, 2, 65535), (16, 500, 6, 3), (6, 1000, 3, 9),
+                                     (4, 1024, 16, 2)])
 def test_generation_matches_reference(N, d, m, g):
     dev = device()
     seed = 99 + N
@@ -138,3 +140,38 @@ def test_realtime_arrivals_latency():
         r = out[q["rid"]]
         assert r["status"] == nsga3.OK
         assert r["latency_s"] > 0 and r["done_s"] >= q["arrival"]
+
+
+def test_mixed_width_batch_equals_alone():
+    """Slots with narrow (d <= 64) and wide decision vectors in one generation
+    step give exactly what each gives alone."""
+    dev = device()
+    shapes = [(40, 12, 3), (33, 500, 6), (9, 1000, 2), (17, 64, 5)]
+    bufs, As = [], []
+    for b, (N, d, m) in enumerate(shapes):
+        A = to_dev(np.random.default_rng(b).standard_normal((m, d - 1)).astype(np.float32), dev)
+        X0, F0 = _buffers(dev, 2 * N, d, m)
+        nsga3.evolve(nsga3.EVOLVE_INIT, N, d, m, A, 7 + b, 0, X0, F0)
+        bufs.append((X0, F0))
+        As.append(A)
+
+    def step(idx):
+        slots = (nsga3.EvolveSlot * len(idx))()
+        outs = []
+        for e, b in zip(slots, idx):
+            N, d, m = shapes[b]
+            X1, F1 = _buffers(dev, 2 * N, d, m)
+            outs.append((X1, F1))
+            e.X_old, e.F_old, e.sel = bufs[b][0].data_ptr(), bufs[b][1].data_ptr(), None
+            e.X_new, e.F_new, e.A = X1.data_ptr(), F1.data_ptr(), As[b].data_ptr()
+            e.N, e.d, e.m, e.generation, e.seed = N, d, m, 4, 7 + b
+            e.mode, e.reserved = nsga3.EVOLVE_GENERATION, 0
+        buf = torch.empty(nsga3.evolve_workspace_bytes(len(idx)), dtype=torch.uint8, device=dev)
+        nsga3.evolve_batched(slots, buf, device=dev)
+        torch.cuda.synchronize()
+        return [(to_np(x).copy(), to_np(f).copy()) for x, f in outs]
+
+    mixed = step(list(range(len(shapes))))
+    for b in range(len(shapes)):
+        alone = step([b])[0]
+        assert np.array_equal(alone[0], mixed[b][0]) and np.array_equal(alone[1], mixed[b][1]), b

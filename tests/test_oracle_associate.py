@@ -11,7 +11,7 @@ def all_st(M):
     return np.zeros(M, np.int32), np.array([0, 0, M, 1], np.int32)
 
 
-@pytest.mark.parametrize("m,p", [(2, 9), (3, 12), (5, 6), (10, 3)])
+@pytest.mark.parametrize("m,p", [(2, 9), (3, 12), (5, 6), (10, 3), (32, 2), (128, 1), (512, 1)])
 def test_points_on_reference_directions(m, p):
     Z = wl.das_dennis(m, p)
     H = len(Z)

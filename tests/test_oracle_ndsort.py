@@ -33,7 +33,7 @@ def brute_ranks(F):
 
 
 @pytest.mark.parametrize("kind", ["continuous", "grid", "chain", "equal"])
-@pytest.mark.parametrize("M,m", [(2, 2), (7, 2), (33, 3), (64, 4), (50, 6)])
+@pytest.mark.parametrize("M,m", [(2, 2), (7, 2), (33, 3), (64, 4), (50, 6), (40, 32), (24, 512)])
 def test_brute_force(kind, M, m):
     rng = np.random.default_rng(M * 100 + m)
     for trial in range(3):

@@ -11,7 +11,7 @@ def all_st(M):
     return np.zeros(M, np.int32), np.array([0, 0, M, 1], np.int32)
 
 
-@pytest.mark.parametrize("m", [2, 3, 5, 10])
+@pytest.mark.parametrize("m", [2, 3, 5, 10, 32, 128, 512])
 def test_axis_points_give_identity(m):
     # unit axis points present, everything else >= 0.01 in every objective:
     # ideal 0, extremes are the axis points, intercepts 1, Fn == F
@@ -158,3 +158,26 @@ def test_tiny_intercept_relative_to_span(far, degen):
         assert np.array_equal(r["intercept"], np.array([2.0, 2.0, far]))
     else:
         assert np.array_equal(r["intercept"], np.array([1.0, 1.0, 2.0 ** -19]))
+
+
+@pytest.mark.parametrize("m", [32, 64, 200])
+def test_many_objective_intercepts_match_library_solve(m):
+    # extreme rows near the axes (axis k at 1 + u_k, off-axis values below
+    # 1e-7, so that 1e6 times them stays below 1) plus far points: the
+    # oracle's extremes are those rows and its intercepts solve the same
+    # system as numpy's LU
+    rng = np.random.default_rng(m)
+    E = 1e-7 * rng.random((m, m)) + np.diag(1.0 + rng.random(m))
+    zero_rest = np.zeros(m)
+    zero_rest[0] = 3.0            # objectives 2..m reach 0 here (ASF_1 = 3)
+    zero_first = np.full(m, 3.0)
+    zero_first[0] = 0.0           # objective 1 reaches 0 here
+    far = 0.5 + rng.random((40, m))
+    F = np.concatenate([E, [zero_rest, zero_first], far]).astype(np.float32)
+    rank, fi = all_st(len(F))
+    r = oracle.normalize(F, rank, fi)
+    assert np.array_equal(r["ideal"], np.zeros(m))
+    assert list(r["extreme"]) == list(range(m))
+    b = np.linalg.solve(F[:m].astype(np.float64), np.ones(m))
+    assert r["degenerate"] == 0
+    np.testing.assert_allclose(1.0 / r["intercept"], b, rtol=1e-10)

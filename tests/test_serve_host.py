@@ -55,3 +55,49 @@ def test_served_trace_shape():
         assert q["A"].shape == (q["m"], q["d"] - 1)
     H = {q["m"]: len(q["Z"]) for q in tr}
     assert H == {3: 861, 5: 495, 10: 220, 15: 135}
+
+
+def _admission(arrivals, sizes, capacity, max_bypass):
+    """Drive admit_arrived over a fake pool of `capacity` units where nothing
+    is released; returns the admission order."""
+    import collections
+
+    queue = collections.deque(dict(rid=i, arrival=a, size=s)
+                              for i, (a, s) in enumerate(zip(arrivals, sizes)))
+    used = [0]
+    order = []
+
+    def try_admit(q):
+        if q["size"] > capacity:
+            return None
+        if used[0] + q["size"] > capacity:
+            return False
+        used[0] += q["size"]
+        order.append(q["rid"])
+        return True
+
+    passed = {}
+    n = serve.admit_arrived(queue, 10.0, try_admit, passed, max_bypass)
+    return order, n, passed, [q["rid"] for q in queue]
+
+
+def test_admission_lets_fitting_requests_pass_a_blocked_one():
+    # request 1 (size 8) does not fit after request 0 (size 5) of capacity 10;
+    # the small requests behind it pass it
+    order, n, passed, left = _admission([0, 1, 2, 3], [5, 8, 1, 2], 10, max_bypass=8)
+    assert order == [0, 2, 3] and left == [1]
+    assert n == 2 and passed == {1: 2}
+
+
+def test_admission_bypass_is_bounded():
+    # after two requests passed it, the blocked request holds the queue
+    order, n, passed, left = _admission([0, 1, 2, 3, 4], [5, 8, 1, 1, 1], 10, max_bypass=2)
+    assert order == [0, 2, 3] and left == [1, 4] and passed == {1: 2}
+    # strict FIFO with no bypass at all
+    order, _, _, left = _admission([0, 1, 2], [5, 8, 1], 10, max_bypass=0)
+    assert order == [0] and left == [1, 2]
+
+
+def test_admission_drops_what_can_never_fit_and_waits_for_arrivals():
+    order, _, _, left = _admission([0, 1, 20], [1, 50, 1], 10, max_bypass=8)
+    assert order == [0] and left == [2]
