@@ -47,6 +47,23 @@ def association_report(Fn64, Z, st, pi_gpu, pi_ref, d_gpu, d_ref, band=1e-6):
     return len(mis), flagged, float(derr.max()) if len(st) else 0.0
 
 
+def near_tie_points(Fn64, Z, st, band=1e-6, chunk=4096):
+    """Number of rows of st whose two nearest references (FP64 perpendicular
+    distance) are within band * ||f||: the only rows at which an FP32
+    association may pick another reference than the FP64 one."""
+    W = Z.astype(np.float64)
+    W = W / np.linalg.norm(W, axis=1, keepdims=True)
+    n = 0
+    for a in range(0, len(st), chunk):
+        f = Fn64[st[a:a + chunk]].astype(np.float64)
+        nf = np.linalg.norm(f, axis=1)
+        p = f @ W.T
+        d = np.sqrt(np.maximum(nf[:, None] ** 2 - p * p, 0.0))
+        two = np.partition(d, 1, axis=1)[:, :2] if d.shape[1] > 1 else np.concatenate([d, d + np.inf], 1)
+        n += int(np.sum(np.abs(two[:, 1] - two[:, 0]) <= band * (1 + 1e-6) * np.maximum(nf, 1e-30)))
+    return n
+
+
 def front_info_of(rank, N):
     """front_info = (l, |S|, K, l + 1) implied by 0-based ranks and N."""
     ranked = rank[rank != 0x7FFFFFFF]
@@ -76,7 +93,7 @@ def select_parity(inst, g, dev):
       - the selection equals the oracle's niching of the GPU's own
         (rank, pi, dist), always, and the pure-FP64 oracle's selection when
         nothing upstream was flagged.
-    Returns dict(ext_ties, pi_ties, dist_err, n_st, identical)."""
+    Returns dict(ext_ties, pi_ties, dist_err, n_st, identical, st, Fn)."""
     import oracle
     from paper_2504_06067_amd import nsga3
 
@@ -108,4 +125,4 @@ def select_parity(inst, g, dev):
     if ext_ties == 0 and pi_ties == 0:
         assert identical, "selection differs from the FP64 oracle with nothing flagged"
     return dict(ext_ties=ext_ties, pi_ties=pi_ties, dist_err=derr, n_st=len(st),
-                identical=identical)
+                identical=identical, st=st, Fn=np.nan_to_num(nrm["Fn"], nan=0.0))
