@@ -48,7 +48,6 @@ Layout make_layout(int M, int m, int H, int N) {
     L.picked = take(Mp * 4);
     L.tcnt = take((Mp + COMPACT_TILE - 1) / COMPACT_TILE * 4);
     L.remain = take((W + (size_t)H + 2) * 8);
-    L.adone = take(W * 4);
     L.emat = take(m > NARROW_M ? ((size_t)m * m + 3 * (size_t)m) * 8 : 0);
     L.total = o;
     return L;
@@ -78,7 +77,6 @@ Ptrs carve(const Layout &L, void *ws) {
     P.picked = (int *)(b + L.picked);
     P.tcnt = (int *)(b + L.tcnt);
     P.remain = (u64 *)(b + L.remain);
-    P.adone = (int *)(b + L.adone);
     P.emat = (double *)(b + L.emat);
     return P;
 }

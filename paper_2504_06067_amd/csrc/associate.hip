@@ -13,10 +13,9 @@
 //
 // Kernels:
 //   k_assoc_list   (stage call) S_t list, key init, pi = dist = -1 outside S_t
-//   k_associate    the fused sweep; the last slice of each block of list
-//                  entries writes pi and dist from the merged keys and, in a
-//                  whole selection, the niche counts rho (fronts < l) and c
-//                  (front l)
+//   k_associate    the fused sweep; slices merge by a 64-bit atomic min
+//   k_assoc_final  pi and dist from the merged keys; in a whole selection
+//                  also the niche counts rho (fronts < l) and c (front l)
 #include "nsga3_internal.h"
 
 namespace nsga3 {
@@ -31,7 +30,6 @@ __global__ __launch_bounds__(256) void k_assoc_list(BatchView bv) {
         I.pi[t] = -1;
         I.dist[t] = -1.0f;
     }
-    if ((t & 63) == 0 && t < I.Mp) I.P.adone[t >> 6] = 0;
     const u64 bal = ballot(in);
     if (bal == 0) return;
     int base = 0;
@@ -62,24 +60,28 @@ __device__ __forceinline__ void assoc_ref(const float (&f)[MO], const NSGA3_RO f
 }
 
 // Merges a wave's best (d^2, reference) of its slice into the keys of its
-// 64 list entries; the last slice of the block to finish reads the merged
-// keys: pi, dist and, in a whole selection, the niche counts rho (fronts < l)
-// and c (front l). Release: the minima are performed before the count; the
-// last wave acquires them all.
-__device__ __forceinline__ void assoc_merge(const BatchView &bv, CInst &I, int pb, int x, bool in,
-                                            bool any, float best, int bj) {
+// 64 list entries: least distance, then least reference index. A fence per
+// wave to let the last slice read the merged keys would write back the L2
+// cache of the wave's XCD every time; the keys are read by k_assoc_final,
+// after the launch boundary, instead.
+__device__ __forceinline__ void assoc_merge(CInst &I, int x, bool in, bool any, float best,
+                                            int bj) {
     if (in && any) {
         const u64 key = ((u64)__float_as_uint(best) << 32) | (unsigned)bj;
         atomicMin(&I.P.akey[x], key);
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    int done = 0;
-    if (lane_id() == 0)
-        done = __hip_atomic_fetch_add(&I.P.adone[pb], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (uniform(done) != I.nslice - 1) return;
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    if (!in) return;
-    const u64 key = load_relaxed(&I.P.akey[x]);
+}
+
+// pi and dist from the merged keys; in a whole selection also the niche
+// counts rho (fronts < l) and c (front l). Grid: padded points of all
+// instances (list positions).
+__global__ __launch_bounds__(256) void k_assoc_final(BatchView bv) {
+    const Local L = locate(bv.pt_pref, bv.B);
+    CInst &I = bv.tab[L.b];
+    const int n = I.P.ctrl->list_count;
+    if (L.i >= n) return;
+    const int x = I.P.list[L.i];
+    const u64 key = I.P.akey[x];
     int jm = (int)(unsigned)(key & 0xffffffffull);
     if (jm < 0 || jm >= I.H) {
         atomicOr(&I.P.ctrl->status, ST_INTERNAL);
@@ -141,7 +143,7 @@ __global__ __launch_bounds__(256) void k_associate(BatchView bv, int gs, int gn,
         assoc_ref<MO>(f, wn, Hp, j + 3, best, bj);
     }
     for (; j < h1; ++j) assoc_ref<MO>(f, wn, Hp, j, best, bj);
-    assoc_merge(bv, I, pb, x, in, h0 < h1, best, bj);
+    assoc_merge(I, x, in, h0 < h1, best, bj);
 }
 
 // Association for m > NARROW_M: the same work items (64 list entries in the
@@ -229,7 +231,7 @@ __global__ __launch_bounds__(256) void k_associate_wide(BatchView bv, int gs, in
         for (int r = 0; r < AW_RG; ++r)
             if (r < ng && d2[r] < best) { best = d2[r]; bj = g0 + r; }
     }
-    assoc_merge(bv, I, pb, x, in, h0 < h1, best, bj);
+    assoc_merge(I, x, in, h0 < h1, best, bj);
 }
 
 hipError_t launch_associate(const HostPlan &hp, const BatchView &bv, hipStream_t s) {
@@ -257,6 +259,7 @@ hipError_t launch_associate(const HostPlan &hp, const BatchView &bv, hipStream_t
         }
 #undef NSGA3_ASSOC_CASE
     }
+    NSGA3_LAUNCH("assoc_final", k_assoc_final, dim3(pblocks), dim3(256), 0, s, bv);
     return hipGetLastError();
 }
 

@@ -40,8 +40,12 @@ __global__ __launch_bounds__(256) void k_prep(BatchView bv, int npt) {
         // objective over all points: a point that attains the least value
         // and is not dominated among those that attain it is not dominated
         // at all, so it is in front 0 and the least value over S_t is the
-        // same float. One atomic per wave and objective.
-        const bool ideal_here = (bv.run & RUN_ND) && (bv.run & RUN_NORM);
+        // same float. Reduced per wave, then per block in LDS: one atomic
+        // per block and objective (atomics on one address serialize).
+        const bool ideal_here = (bv.run & RUN_ND) && (bv.run & RUN_NORM) && m <= NARROW_M;
+        __shared__ unsigned s_lo[4][NARROW_M];
+        const int wv = threadIdx.x >> 6;
+        if (ideal_here && lane_id() < m) s_lo[wv][lane_id()] = 0xffffffffu;
         if (j < Mp && (bv.run & RUN_ND)) {
             for (int k = 0; k < m; ++k) {
                 float v = INFINITY;
@@ -52,7 +56,7 @@ __global__ __launch_bounds__(256) void k_prep(BatchView bv, int npt) {
                 I.P.ft[((size_t)(j >> 6) * m + k) * 64 + (j & 63)] = v;
                 if (ideal_here) {
                     const unsigned lo = wave_min_u32(j < M ? f2ord(v) : 0xffffffffu);
-                    if (lane_id() == 0 && lo != 0xffffffffu) atomicMin(&I.P.ctrl->zmin_enc[k], lo);
+                    if (lane_id() == 0) s_lo[wv][k] = lo;
                 }
             }
             I.P.nd[j] = 0;
@@ -66,6 +70,15 @@ __global__ __launch_bounds__(256) void k_prep(BatchView bv, int npt) {
                     ring[r * sw] = 0ull;
                     ring[r * sw + 1] = 0ull;
                 }
+            }
+        }
+        if (ideal_here) {
+            // ideal_here and the points branch are uniform over the block
+            lds_barrier();
+            if ((int)threadIdx.x < m) {
+                const int k = threadIdx.x;
+                const unsigned lo = min(min(s_lo[0][k], s_lo[1][k]), min(s_lo[2][k], s_lo[3][k]));
+                if (lo != 0xffffffffu) atomicMin(&I.P.ctrl->zmin_enc[k], lo);
             }
         }
         if (j < M && (bv.run & RUN_NICHE)) {

@@ -39,7 +39,6 @@ __global__ __launch_bounds__(256) void k_norm_reduce(BatchView bv, int wide_only
             I.dist[x] = -1.0f;
         }
     }
-    if ((bv.run & RUN_ASSOC) && (x & 63) == 0 && x < I.Mp) I.P.adone[x >> 6] = 0;
     // per-wave, then per-block reductions: one atomic per block and quantity
     const int lane = lane_id();
     const int wv = threadIdx.x >> 6;
@@ -258,11 +257,10 @@ __global__ __launch_bounds__(256) void k_norm_extreme(BatchView bv, int gs, int 
 // The normalization of a whole selection in one pass over the points (the
 // ideal point already came from the preparation kernel, over all points):
 // the S_t list, the per-objective maximum over S_t, and the ASF extreme
-// search; the association outputs of rows outside S_t and the per-block
-// counters of the association are set up on the way. Every block of an
-// instance's padded point range takes part, and the last to finish solves
-// for the intercepts. Grid: all instances' padded points (one launch per m;
-// blocks of other instances leave at once).
+// search; the association outputs of rows outside S_t are set up on the
+// way. Every block of an instance's padded point range takes part, and the
+// last to finish solves for the intercepts. Grid: all instances' padded
+// points (one launch per m; blocks of other instances leave at once).
 template <int MO>
 __global__ __launch_bounds__(256) void k_norm_fused(BatchView bv) {
     __shared__ unsigned s_hi[4][MO];
@@ -284,7 +282,6 @@ __global__ __launch_bounds__(256) void k_norm_fused(BatchView bv) {
             I.dist[x] = -1.0f;
         }
     }
-    if ((x & 63) == 0 && x < I.Mp) I.P.adone[x >> 6] = 0;
     const int lane = lane_id();
     const int wv = threadIdx.x >> 6;
     const u64 bal = ballot(in);

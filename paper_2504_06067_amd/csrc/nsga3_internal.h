@@ -76,7 +76,7 @@ constexpr int TICKET_STRIDE = 32;   // u64 words between them (256 bytes)
 struct Layout {
     int M, m, H, N, Mp, W, Hp;
     size_t ctrl, ft, nd, mask, ring, list, fn, rank, pi, dist, akey, wn,
-        rho, cnt, off, fill, tpick, members, picked, tcnt, remain, adone, emat, total;
+        rho, cnt, off, fill, tpick, members, picked, tcnt, remain, emat, total;
 };
 
 Layout make_layout(int M, int m, int H, int N);
@@ -96,7 +96,6 @@ struct Ptrs {
     int *rho, *cnt, *off, *fill, *tpick, *members, *picked;
     int *tcnt;          // selected points per compaction tile
     u64 *remain;
-    int *adone;         // association: slices merged per block of 64 list entries
     double *emat;       // m > NARROW_M: the intercept system [m][m], rhs, column maxima, b
 };
 
