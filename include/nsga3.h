@@ -137,6 +137,31 @@ int nsga3_select(const float *F, int32_t M, int32_t m, const float *Z, int32_t H
                  int32_t *pi_out, float *dist_out,
                  void *ws, size_t ws_bytes, void *stream);
 
+/* ------------------------------------------------------------ no alloc
+ * For callers that cannot allocate device memory or pass a workspace: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc. nsga3_select with the library's own scratch instead of `ws`:
+ * a device array of NSGA3_NOALLOC_SCRATCH_BYTES per GPU, part of the
+ * library's code object, held by each GPU the library runs on until the
+ * process ends (its address is looked up once per device, at the first call
+ * with that device current). The call allocates nothing and enqueues kernels
+ * only.
+ *  - Arguments as nsga3_select. Returns NSGA3_EINVAL for the same bad
+ *    arguments, and NSGA3_EWORKSPACE when nsga3_workspace_bytes(M, m, H, N)
+ *    exceeds NSGA3_NOALLOC_SCRATCH_BYTES (e.g. m = 3 holds up to about
+ *    M = 22800); nothing is enqueued in either case.
+ *  - status: int32[1] device memory or NULL; receives the device-detected
+ *    status of the call (the codes of nsga3_read_status) when its work ends.
+ *  - Every call on one GPU shares that GPU's scratch, whatever the stream:
+ *    calls that overlap in time on one GPU race and give undefined results.
+ *    Serialize them (one stream, or events). The scratch keeps the last
+ *    call's contents; each call initializes what it needs itself. */
+#define NSGA3_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+
+int nsga3_select_noalloc(const float *F, int32_t M, int32_t m, const float *Z, int32_t H,
+                         int32_t N, uint64_t seed, int32_t *selected, int32_t *rank_out,
+                         int32_t *pi_out, float *dist_out, int32_t *status, void *stream);
+
 /* ------------------------------------------------------------- batching
  * Many independent selections in one call: every stage runs once over all
  * instances (one grid per kernel, instances of equal m share a launch), so

@@ -10,6 +10,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 #include "nsga3_internal.h"
@@ -439,6 +440,49 @@ static int status_code(int bits) {
     return NSGA3_OK;
 }
 
+// ------------------------------------------------------ no-alloc scratch
+
+// The workspace of nsga3_select_noalloc: a device array of the library, one
+// copy per GPU, held until the process ends. Host code never passes `scratch`
+// itself to a kernel (in host code it names a host-side stand-in); it uses
+// the device address that hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) unsigned char scratch[NSGA3_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+char *g_scratch[MAX_DEVICES];
+}  // namespace
+
+// The device address of `scratch` on the current device, looked up once per
+// device (with that device current) and kept.
+static hipError_t scratch_of_current_device(char **out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!ptr || !aligned(ptr, 256)) return hipErrorInvalidSymbol;
+        g_scratch[dev] = (char *)ptr;
+    }
+    *out = g_scratch[dev];
+    return hipSuccess;
+}
+
+// The public status code of an instance, from its control block.
+__global__ void k_status_out(const Ctrl *ctrl, int *status) {
+    if (threadIdx.x != 0) return;
+    const int bits = ctrl->status;
+    *status = (bits & ST_NONFINITE)  ? NSGA3_ENONFINITE
+              : (bits & ST_BADREF)   ? NSGA3_EINVAL
+              : (bits & ST_INTERNAL) ? NSGA3_EINTERNAL
+                                     : NSGA3_OK;
+}
+
 // ---------------------------------------------------------- instrumentation
 
 namespace {
@@ -580,6 +624,40 @@ int nsga3_select(const float *F, int32_t M, int32_t m, const float *Z, int32_t H
     std::vector<Spec> v;
     specs_of(&q, 1, v);
     return run_select(v, ws, ws_bytes, (hipStream_t)stream);
+}
+
+int nsga3_select_noalloc(const float *F, int32_t M, int32_t m, const float *Z, int32_t H,
+                         int32_t N, uint64_t seed, int32_t *selected, int32_t *rank_out,
+                         int32_t *pi_out, float *dist_out, int32_t *status, void *stream) {
+    nsga3_instance q;
+    memset(&q, 0, sizeof(q));
+    q.F = F;
+    q.Z = Z;
+    q.selected = selected;
+    q.rank = rank_out;
+    q.pi = pi_out;
+    q.dist = dist_out;
+    q.M = M;
+    q.m = m;
+    q.H = H;
+    q.N = N;
+    q.seed = seed;
+    if (!valid_instance(q) || (status && !aligned(status, 4))) return NSGA3_EINVAL;
+    std::vector<Spec> v;
+    specs_of(&q, 1, v);
+    {
+        Plan p;
+        plan(v, nullptr, RUN_SELECT, p);
+        if (p.total > NSGA3_NOALLOC_SCRATCH_BYTES) return NSGA3_EWORKSPACE;
+    }
+    char *ws = nullptr;
+    if (scratch_of_current_device(&ws) != hipSuccess) return NSGA3_EHIP;
+    hipStream_t s = (hipStream_t)stream;
+    const int rc = run_select(v, ws, NSGA3_NOALLOC_SCRATCH_BYTES, s);
+    if (rc != NSGA3_OK || !status) return rc;
+    // instance 0's control block sits at the start of the scratch
+    NSGA3_LAUNCH("status", k_status_out, dim3(1), dim3(64), 0, s, (const Ctrl *)ws, status);
+    return to_status(hipGetLastError());
 }
 
 size_t nsga3_instance_workspace_bytes(int32_t M, int32_t m, int32_t H, int32_t N) {

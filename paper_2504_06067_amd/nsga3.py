@@ -44,6 +44,7 @@ def lib():
     L.nsga3_associate.argtypes = [P, P, P, i32, i32, P, i32, P, P, P, sz, P]
     L.nsga3_niche.argtypes = [P, P, P, P, i32, i32, i32, u64, P, P, sz, P]
     L.nsga3_select.argtypes = [P, i32, i32, P, i32, i32, u64, P, P, P, P, P, sz, P]
+    L.nsga3_select_noalloc.argtypes = [P, i32, i32, P, i32, i32, u64, P, P, P, P, P, P]
     L.nsga3_read_status.argtypes = [P, P, P]
     L.nsga3_batched_workspace_bytes.argtypes = [P, i32]
     L.nsga3_batched_workspace_bytes.restype = sz
@@ -58,7 +59,7 @@ def lib():
     L.nsga3_profile_enable.argtypes = [ctypes.c_char_p]
     L.nsga3_profile_read.argtypes = [ctypes.c_char_p, P, P, P]
     for f in ("nsga3_nd_sort", "nsga3_normalize", "nsga3_associate", "nsga3_niche",
-              "nsga3_select", "nsga3_read_status", "nsga3_profile_enable", "nsga3_profile_read",
+              "nsga3_select", "nsga3_select_noalloc", "nsga3_read_status", "nsga3_profile_enable", "nsga3_profile_read",
               "nsga3_select_batched", "nsga3_read_status_batched", "nsga3_evolve_batched"):
         getattr(L, f).restype = i32
     _lib = L
@@ -215,6 +216,35 @@ def select(F, Z, N, seed, ws=None, out=None, intermediates=False):
     if intermediates:
         return dict(selected=sel, rank=rank, pi=pi, dist=dist)
     return sel
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20
+
+
+def select_noalloc(F, Z, N, seed, intermediates=False):
+    """The whole selection on the library's own per-GPU scratch (no workspace
+    argument; calls on one GPU must not overlap). Returns (selected, status)
+    or, with intermediates=True, (dict(selected, rank, pi, dist), status);
+    status is an int32[1] CUDA tensor that receives the call's status code."""
+    F, Z = _f32(F, "F", 2), _f32(Z, "Z", 2)
+    M, m = F.shape
+    H = Z.shape[0]
+    if Z.shape[1] != m:
+        raise ValueError("Z must have m columns")
+    dev = F.device
+    sel = torch.empty(int(N), dtype=torch.int32, device=dev)
+    st = torch.empty(1, dtype=torch.int32, device=dev)
+    rank = pi = dist = None
+    if intermediates:
+        rank = torch.empty(M, dtype=torch.int32, device=dev)
+        pi = torch.empty(M, dtype=torch.int32, device=dev)
+        dist = torch.empty(M, dtype=torch.float32, device=dev)
+    _check(lib().nsga3_select_noalloc(_ptr(F), M, m, _ptr(Z), H, int(N), int(seed) & (2**64 - 1),
+                                      _ptr(sel), _ptr(rank), _ptr(pi), _ptr(dist), _ptr(st),
+                                      _stream(dev)), "nsga3_select_noalloc")
+    if intermediates:
+        return dict(selected=sel, rank=rank, pi=pi, dist=dist), st
+    return sel, st
 
 
 class Instance(ctypes.Structure):

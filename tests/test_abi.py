@@ -73,6 +73,21 @@ def test_invalid_arguments_enqueue_nothing(lib):
                             None) == -1
 
 
+def test_noalloc_validates_before_enqueue(lib):
+    P, i32 = ctypes.c_void_p, ctypes.c_int32
+    f = lib.nsga3_select_noalloc
+    f.argtypes = [P, i32, i32, P, i32, i32, ctypes.c_uint64, P, P, P, P, P, P]
+    assert f(None, 10, 3, None, 5, 5, 0, None, None, None, None, None, None) == -1
+    fake = P(4096)  # never dereferenced: validation fails first
+    assert f(fake, 10, 513, fake, 5, 5, 0, fake, None, None, None, None, None) == -1
+    assert f(fake, 10, 3, fake, 5, 5, 0, fake, None, None, None, P(4098), None) == -1  # status
+    # beyond the 64 MiB scratch (m = 3, M = 30000 needs about 109 MiB)
+    assert lib.nsga3_workspace_bytes(30000, 3, 5, 15000) > 64 << 20
+    assert f(fake, 30000, 3, fake, 5, 15000, 0, fake, None, None, None, None, None) == -2
+    src = open(HEADER).read()
+    assert "#define NSGA3_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)" in src
+
+
 class _Inst(ctypes.Structure):
     _fields_ = [("F", ctypes.c_void_p), ("Z", ctypes.c_void_p), ("selected", ctypes.c_void_p),
                 ("rank", ctypes.c_void_p), ("pi", ctypes.c_void_p), ("dist", ctypes.c_void_p),
