@@ -20,6 +20,8 @@ resident in HBM before the timed region. The JSON line reports
   batched         64 uneven instances, one graph replay vs 64 plain calls
   served          continuous batching vs the one-at-a-time plain loop on the
                   same Poisson trace, per offered load
+  niche_ab        the niche stage alone: the closed form against the paper's
+                  cache-tensor loop, on each workload's own GPU intermediates
   cpu_baseline    the FP64 CPU oracle on a bounded sample of the same workload,
                   single-threaded and on all usable cores
   parity          per workload, from the oracle run in the CPU-baseline leg:
@@ -352,6 +354,7 @@ def bench_served(args, dev):
               f"p50 x{points[-1]['speedup_p50']:.2f}, p99 x{points[-1]['speedup_p99']:.2f}",
               file=sys.stderr, flush=True)
     first = points[0]
+    quality = served_quality(dev, trace, results["batched"])
     return {
         "workload": f"{R} requests, Poisson arrivals, 2N log-uniform [1000, 100000], m in "
                     f"{{3,5,10,15}}, d=12, {G} generations each (SBX + polynomial mutation + "
@@ -365,7 +368,43 @@ def bench_served(args, dev):
         "speedup_p50": first["speedup_p50"], "speedup_p99": first["speedup_p99"],
         "results_identical": all(p["results_identical"] for p in points),
         "sweep": points,
+        "quality": quality,
     }
+
+
+def served_quality(dev, trace, results, samples=1 << 16):
+    """Quality of every served run's final population, computed on the
+    device: IGD against the run's unit reference directions (points of the
+    synthetic law's optimal front, the unit sphere), and the normalized
+    hypervolume of the paper's box for that front (f_min = 0, f_max = 1:
+    ideal 0, reference point 1.01), from `samples` sample points. Means per
+    objective count."""
+    import numpy as np
+    import torch
+
+    from paper_2504_06067_amd import nsga3
+
+    by_m = {}
+    t0 = time.perf_counter()
+    for q in trace:
+        F = torch.from_numpy(np.ascontiguousarray(results[q["rid"]]["F"])).to(dev)
+        Z = np.asarray(q["Z"], np.float64)
+        R = torch.from_numpy((Z / np.linalg.norm(Z, axis=1, keepdims=True)).astype(np.float32)).to(dev)
+        m = F.shape[1]
+        igd = nsga3.igd(F, R)
+        hv = nsga3.hv_count(F, [0.0] * m, [1.01] * m, samples, q["rid"])
+        torch.cuda.synchronize(dev)
+        e = by_m.setdefault(m, {"runs": 0, "igd": [], "hv": []})
+        e["runs"] += 1
+        e["igd"].append(float(igd.cpu()[0]))
+        e["hv"].append(int(hv.cpu()[0]) / samples)
+    out = {"front": "unit sphere (the synthetic law's optimum); HV box ideal 0, ref 1.01",
+           "hv_samples": samples, "seconds": time.perf_counter() - t0, "by_m": {}}
+    for m, e in sorted(by_m.items()):
+        out["by_m"][str(m)] = {"runs": e["runs"], "igd_mean": float(np.mean(e["igd"])),
+                               "igd_max": float(np.max(e["igd"])),
+                               "hv_norm_mean": float(np.mean(e["hv"]))}
+    return out
 
 
 # Per-generation runtime of TensorNSGA-III in the paper's Table I (V100 + EPYC
@@ -603,6 +642,60 @@ def latency_leg(name, dev, seed, reps, warmup):
     return out, inst, r["gpu_out"]
 
 
+def bench_niche_ab(dev, legs, reps=30):
+    """The niche stage alone on each workload's own (rank, front_info, pi,
+    dist) from the GPU: the closed form (nsga3_niche) against the paper's
+    cache-tensor loop (nsga3_niche_cache_tensor); per-call p50 and the
+    kernel times of each, and whether the selections are identical."""
+    import numpy as np
+    import torch
+
+    from paper_2504_06067_amd import nsga3
+
+    out = {}
+    stream = torch.cuda.current_stream(dev)
+    for name, (inst, g) in legs.items():
+        rank, pi, dist = g["rank"], g["pi"], g["dist"]
+        rk = rank.cpu().numpy()
+        l = int(rk[rk != nsga3.UNRANKED].max())
+        S = int(np.sum(rk < l))
+        fi = torch.tensor([l, S, inst["N"] - S, l + 1], dtype=torch.int32, device=dev)
+        res = {"l": l, "S": S, "K": inst["N"] - S, "H": inst["H"]}
+        sels = {}
+        for label, ct, kern in (("closed_form", False, "niche_scatter,niche_plan,niche_pick,compact"),
+                                ("cache_tensor", True, "niche_scatter,ct_offsets,ct_order,ct_loop,compact")):
+            ws = nsga3.Workspace(dev)
+            for _ in range(3):
+                nsga3.niche(rank, fi, pi, dist, inst["H"], inst["N"], inst["seed"], ws=ws,
+                            cache_tensor=ct)
+            torch.cuda.synchronize(dev)
+            ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                  for _ in range(reps)]
+            nsga3.profile_enable(kern)
+            for a, b in ev:
+                a.record(stream)
+                sel = nsga3.niche(rank, fi, pi, dist, inst["H"], inst["N"], inst["seed"], ws=ws,
+                                  cache_tensor=ct)
+                b.record(stream)
+            torch.cuda.synchronize(dev)
+            kt = {}
+            for k in kern.split(","):
+                ms, n, _ = nsga3.profile_read(k)
+                kt[k] = round(ms / max(n, 1) * 1e3, 2)
+            nsga3.profile_enable(None)
+            ms = np.array([a.elapsed_time(b) for a, b in ev])
+            res[label] = {"p50_us": float(np.percentile(ms, 50)) * 1e3, "kernels_avg_us": kt,
+                          "status": ws.status()}
+            sels[label] = sel.cpu().numpy()
+        res["identical"] = bool(np.array_equal(sels["closed_form"], sels["cache_tensor"]))
+        res["speedup_closed_form"] = res["cache_tensor"]["p50_us"] / res["closed_form"]["p50_us"]
+        out[name] = res
+        print(f"niche A/B {name}: closed form {res['closed_form']['p50_us']:.1f} us, cache tensor "
+              f"{res['cache_tensor']['p50_us']:.1f} us, identical {res['identical']}",
+              file=sys.stderr, flush=True)
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -691,6 +784,10 @@ def main():
         res["many_objective"] = many
         legs = {"small": (small_inst, small_out), "many_objective": (many_inst, many_out)}
         print("timed the small and many-objective workloads", file=sys.stderr, flush=True)
+    if legs or main_out is not None:
+        ab_legs = {args.workload: (inst, main_out)}
+        ab_legs.update({k: v for k, v in legs.items() if k != "small"})
+        res["niche_ab"] = bench_niche_ab(dev, ab_legs)
     if not args.no_generations:
         res["generation_loop"] = bench_generation_loop(args, dev)
     if not args.no_objective_scaling:

@@ -129,6 +129,19 @@ int nsga3_niche(const int32_t *rank, const int32_t *front_info, const int32_t *p
                 const float *dist, int32_t M, int32_t H, int32_t N, uint64_t seed,
                 int32_t *selected, void *ws, size_t ws_bytes, void *stream);
 
+/* The same niche stage as the paper states it (Algorithm 2: nearest
+ * selection, then the random selection loop over the cache tensor Q), kept
+ * as a baseline to compare with nsga3_niche's closed form on the same GPU.
+ * Row j of Q lists the last-front candidates of reference j in the order
+ * reference j picks them (nearest first at niche count 0, then the keyed
+ * random picks); the loop lets every least-crowded reference take its next
+ * row entry per iteration, until K are taken, the last iteration keeping the
+ * references with the least tag-1 keys. Same arguments, workspace and
+ * result as nsga3_niche (bit for bit). */
+int nsga3_niche_cache_tensor(const int32_t *rank, const int32_t *front_info, const int32_t *pi,
+                             const float *dist, int32_t M, int32_t H, int32_t N, uint64_t seed,
+                             int32_t *selected, void *ws, size_t ws_bytes, void *stream);
+
 /* The whole selection: nd_sort(n_stop = N) -> normalize -> associate ->
  * niche. rank_out int32[M], pi_out int32[M] and dist_out float32[M] may be
  * NULL; when given they receive the intermediate results. */
@@ -269,6 +282,31 @@ size_t nsga3_evolve_workspace_bytes(int32_t B);
  * Returns NSGA3_EINVAL (nothing enqueued) for a bad slot. */
 int nsga3_evolve_batched(const nsga3_evolve_slot *slots, int32_t B, void *ws, size_t ws_bytes,
                          void *stream);
+
+/* ---------------------------------------------------- quality indicators
+ * Measures of what a run produced (not part of the selection), for the
+ * paper's quality studies: IGD (Sec. IV, population size against IGD) and
+ * the normalized hypervolume of Appendix E. F is a population [n][m]
+ * float32, 1 <= n <= 2^20, 2 <= m <= 16.
+ *
+ * IGD: the mean over the points r of R [nr][m] (points of the optimal
+ * front) of min over the population of ||r - f||_2, distances in FP32, the
+ * mean in FP64 in a fixed order. *igd (device double) receives it. ws is a
+ * device buffer of nsga3_igd_workspace_bytes(nr) bytes, 256-byte aligned. */
+size_t nsga3_igd_workspace_bytes(int32_t nr);
+int nsga3_igd(const float *F, int32_t n, int32_t m, const float *R, int32_t nr, double *igd,
+              void *ws, size_t ws_bytes, void *stream);
+
+/* Hypervolume estimate: *count (device uint64) receives the number of the
+ * `samples` sample points of the box [ideal, ref] (ideal, ref: [host] float
+ * arrays of m, ideal_k <= ref_k) that some population point weakly dominates
+ * (f_k <= y_k for every k). The normalized hypervolume HV / HV_max of the
+ * paper is count / samples, with ideal = 0.9 f_min and ref = 1.01 f_max.
+ * Sample i, objective k: u = (sm64(seed ^ sm64(i << 8 | k)) >> 40) * 2^-24
+ * and y_k = ideal_k + u * (ref_k - ideal_k), each FP32 operation rounded
+ * separately (no fused multiply-add). samples in [1, 2^31]. */
+int nsga3_hv_count(const float *F, int32_t n, int32_t m, const float *ideal, const float *ref,
+                   int64_t samples, uint64_t seed, unsigned long long *count, void *stream);
 
 /* Waits for `stream`, then reads the status word of `ws` into *status [host]
  * (NSGA3_OK, NSGA3_ENONFINITE, NSGA3_EINVAL or NSGA3_EINTERNAL). Returns

@@ -17,7 +17,8 @@ LIB = os.path.join(HERE, "libnsga3.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["ndsort.hip", "normalize.hip", "associate.hip", "niche.hip", "evolve.hip", "api.hip"]
+SOURCES = ["ndsort.hip", "normalize.hip", "associate.hip", "niche.hip", "evolve.hip", "quality.hip",
+           "api.hip"]
 
 FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",

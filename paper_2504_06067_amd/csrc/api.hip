@@ -46,6 +46,7 @@ Layout make_layout(int M, int m, int H, int N) {
     L.fill = take(Hp * 4);
     L.tpick = take(Hp * 4);
     L.members = take(Mp * 4);
+    L.qrow = take(Mp * 4);
     L.picked = take(Mp * 4);
     L.tcnt = take((Mp + COMPACT_TILE - 1) / COMPACT_TILE * 4);
     L.remain = take((W + (size_t)H + 2) * 8);
@@ -75,6 +76,7 @@ Ptrs carve(const Layout &L, void *ws) {
     P.fill = (int *)(b + L.fill);
     P.tpick = (int *)(b + L.tpick);
     P.members = (int *)(b + L.members);
+    P.qrow = (int *)(b + L.qrow);
     P.picked = (int *)(b + L.picked);
     P.tcnt = (int *)(b + L.tcnt);
     P.remain = (u64 *)(b + L.remain);
@@ -487,7 +489,6 @@ __global__ void k_status_out(const Ctrl *ctrl, int *status) {
 
 namespace {
 constexpr int PROF_POOL = 8192;   // event pairs per enable
-constexpr int PROF_NAMES = 64;
 struct ProfState {
     bool on = false;
     bool all = false;
@@ -602,6 +603,21 @@ int nsga3_niche(const int32_t *rank, const int32_t *front_info, const int32_t *p
     sp.I.seed = seed;
     sp.I.selected = selected;
     return run_single(sp, ws, ws_bytes, RUN_NICHE, (hipStream_t)stream);
+}
+
+int nsga3_niche_cache_tensor(const int32_t *rank, const int32_t *front_info, const int32_t *pi,
+                             const float *dist, int32_t M, int32_t H, int32_t N, uint64_t seed,
+                             int32_t *selected, void *ws, size_t ws_bytes, void *stream) {
+    if (!rank || !front_info || !pi || !dist || !selected || !valid_shape(M, 2, H, N))
+        return NSGA3_EINVAL;
+    Spec sp = blank_spec(M, 2, H, N);
+    sp.I.rank = (int *)rank;              // read only in this call
+    sp.I.front_info = (int *)front_info;
+    sp.I.pi = (int *)pi;
+    sp.I.dist = (float *)dist;
+    sp.I.seed = seed;
+    sp.I.selected = selected;
+    return run_single(sp, ws, ws_bytes, RUN_NICHE | RUN_CACHE_TENSOR, (hipStream_t)stream);
 }
 
 int nsga3_select(const float *F, int32_t M, int32_t m, const float *Z, int32_t H, int32_t N,

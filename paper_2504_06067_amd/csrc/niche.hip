@@ -25,6 +25,9 @@
 //   k_niche_pick     one wave per reference: sort its segment ascending,
 //                    make its picks with a remaining-set bitmask
 //   k_compact        ascending output of S and the picks
+//   k_ct_offsets, k_ct_loop   the paper's cache-tensor loop (A/B baseline)
+#include <limits.h>
+
 #include "nsga3_internal.h"
 
 namespace nsga3 {
@@ -501,6 +504,11 @@ __device__ __forceinline__ int select_bit(u64 w, int k) {
 // One wave per reference (4 per workgroup). Segments up to PICK_CAP are
 // sorted and tracked in LDS; longer ones in place in global memory.
 // Grid: all instances' padded reference ranges, four references per block.
+// ORDER (the cache-tensor baseline): every candidate of the reference is
+// picked, level after level, and the picks are written in that order to its
+// row of the cache tensor (qrow, the reference's segment of the CSR) instead
+// of being marked selected.
+template <bool ORDER>
 __global__ __launch_bounds__(256) void k_niche_pick(BatchView bv) {
     __shared__ int s_buf[4][PICK_CAP];
     __shared__ u64 s_rem[4][PICK_CAP / 64];
@@ -521,11 +529,22 @@ __global__ __launch_bounds__(256) void k_niche_pick(BatchView bv) {
     const int lane = lane_id();
     const int j = base - bv.ref_pref[b] + wv;
     if (j >= I.H) return;
-    const int t = tpick[j];
+    const int t = ORDER ? cnt[j] : tpick[j];
     if (t <= 0) return;
     const int c = cnt[j];
     int *seg = members + off[j];
-    if (t >= c) {
+    int *qrow = I.P.qrow + off[j];
+    int emitted = 0;  // ORDER: picks written so far
+    // records pick x (lane 0)
+    auto emit = [&](int x) {
+        if (ORDER) {
+            qrow[emitted++] = x;
+        } else {
+            picked[x] = 1;
+            atomicAdd(&tcnt[x / COMPACT_TILE], 1);
+        }
+    };
+    if (!ORDER && t >= c) {
         for (int i = lane; i < c; i += 64) {
             const int x = seg[i];
             picked[x] = 1;
@@ -543,11 +562,7 @@ __global__ __launch_bounds__(256) void k_niche_pick(BatchView bv) {
             best = k < best ? k : best;
         }
         best = wave_min_u64(best);
-        if (lane == 0) {
-            const int x = (int)(unsigned)(best & 0xffffffffull);
-            picked[x] = 1;
-            atomicAdd(&tcnt[x / COMPACT_TILE], 1);
-        }
+        if (lane == 0) emit((int)(unsigned)(best & 0xffffffffull));
         return;
     }
     int *buf;
@@ -606,11 +621,7 @@ __global__ __launch_bounds__(256) void k_niche_pick(BatchView bv) {
                 myrem &= ~(1ull << (pos & 63));
                 own -= 1;
             }
-            if (lane == 0) {
-                const int x = buf[pos];
-                picked[x] = 1;
-                atomicAdd(&tcnt[x / COMPACT_TILE], 1);
-            }
+            if (lane == 0) emit(buf[pos]);
         }
         return;
     }
@@ -658,13 +669,159 @@ __global__ __launch_bounds__(256) void k_niche_pick(BatchView bv) {
         // remove position pos
         if (lane == 0) rem[pos >> 6] &= ~(1ull << (pos & 63));
         if (lane == (pos >> 6) / s) own -= 1;
-        if (lane == 0) {
-            const int x = buf[pos];
-            picked[x] = 1;
-            atomicAdd(&tcnt[x / COMPACT_TILE], 1);
-        }
+        if (lane == 0) emit(buf[pos]);
         wave_sync();
     }
+}
+
+// ------------------------------------------------- cache-tensor baseline
+//
+// The paper's own niche fill (Algorithm 2, nearest selection and the random
+// selection loop over the cache tensor Q), for an A/B comparison with the
+// closed form above; same inputs, same keys, the same selection. Q's row j
+// holds the candidates of reference j in the order reference j picks them
+// (the nearest first at niche count 0, then keyed picks; k_niche_pick<true>),
+// so the row position s_j is the next pick. The rows are the reference's CSR
+// segment (the paper pads them to a dense w x n tensor, which only changes
+// the memory used). Then one workgroup per instance runs the loop: find the
+// least niche count among references with candidates left, let every
+// reference at that count take its next row entry, update the counts, until
+// K are taken; the last iteration keeps the references with the least tag-1
+// keys (the paper truncates the last selection in its shuffled reference
+// order).
+
+// Exclusive scan of c over the references (the CSR offsets of Q's rows), one
+// workgroup per instance.
+__global__ __launch_bounds__(PLAN_THREADS) void k_ct_offsets(BatchView bv) {
+    CInst &I = bv.tab[blockIdx.x];
+    __shared__ int wsum[PLAN_WAVES];
+    __shared__ int s_carry;
+    const int tid = threadIdx.x, wv = tid >> 6, lane = lane_id();
+    const int H = I.H;
+    if (tid == 0) s_carry = 0;
+    lds_barrier();
+    for (int j0 = 0; j0 < H; j0 += PLAN_THREADS) {
+        const int j = j0 + tid;
+        const int c = j < H ? I.P.cnt[j] : 0;
+        const int incl = wave_incl_scan(c);
+        if (lane == 63) wsum[wv] = incl;
+        lds_barrier();
+        int before = uniform(s_carry);
+        for (int v = 0; v < wv; ++v) before += wsum[v];
+        if (j < H) I.P.off[j] = before + incl - c;
+        lds_barrier();
+        if (tid == PLAN_THREADS - 1) s_carry = before + incl;
+        lds_barrier();
+    }
+    if (tid == 0) I.P.off[H] = s_carry;
+}
+
+__device__ __forceinline__ long long block_min_ll(long long v, long long *red) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = min(v, (long long)__shfl_xor(v, o, 64));
+    lds_barrier();
+    if (lane_id() == 0) red[threadIdx.x >> 6] = v;
+    lds_barrier();
+    long long m = LLONG_MAX;
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) m = min(m, red[i]);
+    return uniform(m);
+}
+
+// The selection loop. Reference j's state: its niche count lev_j = rho_j +
+// s_j and its candidates left, left_j = c_j - s_j (s_j picks made); it takes
+// part while left_j > 0. The state lives in LDS when H <= CT_LDS_REFS, else
+// in workspace arrays (tpick, fill: free after the scatter).
+constexpr int CT_LDS_REFS = 12288;
+
+template <bool IN_LDS>
+__device__ void ct_loop(CInst &I, int *lev, int *left) {
+    __shared__ long long red[PLAN_WAVES];
+    __shared__ unsigned hist[256];
+    __shared__ int s_sel[2];
+    const int tid = threadIdx.x;
+    const int H = I.H;
+    const u64 seed = I.seed;
+    const int *__restrict__ cnt = I.P.cnt;
+    const int *__restrict__ off = I.P.off;
+    const int *__restrict__ qrow = I.P.qrow;
+    int *picked = I.P.picked;
+    int *tcnt = I.P.tcnt;
+    const long long K = uniform(I.front_info[2]);
+    for (int j = tid; j < H; j += PLAN_THREADS) {
+        lev[j] = I.P.rho[j];
+        left[j] = cnt[j];
+    }
+    lds_barrier();  // each thread reads back only its own references
+    long long taken = 0;
+    while (taken < K) {
+        // mark tensor u: the references of least niche count with candidates left
+        long long lmin = LLONG_MAX;
+        long long nu = 0;
+        for (int j = tid; j < H; j += PLAN_THREADS)
+            if (left[j] > 0) lmin = min(lmin, (long long)lev[j]);
+        lmin = block_min_ll(lmin, red);
+        if (lmin == LLONG_MAX) {
+            // fewer candidates than K: an inconsistent input
+            if (tid == 0) atomicOr(&I.P.ctrl->status, ST_INTERNAL);
+            break;
+        }
+        for (int j = tid; j < H; j += PLAN_THREADS) nu += (left[j] > 0 && lev[j] == lmin);
+        nu = block_sum_ll(nu, red);
+        // the last iteration keeps the r least tag-1 keys of u: threshold by
+        // radix select, 8 bits per pass from the top
+        const bool trunc = taken + nu > K;
+        u64 thr = ~0ull;
+        if (trunc) {
+            int need = (int)(K - taken);
+            u64 prefix = 0, pmask = 0;
+            for (int shift = 56; shift >= 0; shift -= 8) {
+                for (int q = tid; q < 256; q += PLAN_THREADS) hist[q] = 0;
+                lds_barrier();
+                for (int j = tid; j < H; j += PLAN_THREADS) {
+                    if (!(left[j] > 0 && lev[j] == lmin)) continue;
+                    const u64 key = tie_key(seed, 1u, (unsigned)j, (unsigned)lmin);
+                    if ((key & pmask) == prefix) atomicAdd(&hist[(key >> shift) & 255u], 1u);
+                }
+                lds_barrier();
+                if (tid == 0) {
+                    int acc = 0, d = 255;
+                    for (int q = 0; q < 256; ++q) {
+                        if (acc + (int)hist[q] >= need) { d = q; break; }
+                        acc += (int)hist[q];
+                    }
+                    s_sel[0] = d;
+                    s_sel[1] = need - acc;
+                }
+                lds_barrier();
+                prefix |= (u64)uniform(s_sel[0]) << shift;
+                pmask |= 0xffull << shift;
+                need = uniform(s_sel[1]);
+                lds_barrier();  // s_sel and hist are reused
+            }
+            thr = prefix;  // the r-th least key itself (keys of distinct references differ)
+        }
+        // select Q[j][s_j] for the marked references; their niche counts and
+        // row positions advance
+        for (int j = tid; j < H; j += PLAN_THREADS) {
+            const int lj = left[j];
+            if (!(lj > 0 && lev[j] == lmin)) continue;
+            if (trunc && tie_key(seed, 1u, (unsigned)j, (unsigned)lmin) > thr) continue;
+            const int x = qrow[off[j] + cnt[j] - lj];
+            picked[x] = 1;
+            atomicAdd(&tcnt[x / COMPACT_TILE], 1);
+            left[j] = lj - 1;
+            lev[j] = (int)lmin + 1;
+        }
+        lds_barrier();
+        taken = trunc ? K : taken + nu;
+    }
+}
+
+__global__ __launch_bounds__(PLAN_THREADS) void k_ct_loop(BatchView bv) {
+    __shared__ int s_lev[CT_LDS_REFS], s_left[CT_LDS_REFS];
+    CInst &I = bv.tab[blockIdx.x];
+    if (uniform(I.H) <= CT_LDS_REFS) ct_loop<true>(I, s_lev, s_left);
+    else ct_loop<false>(I, I.P.tpick, I.P.fill);
 }
 
 // Compaction of {x : rank[x] < l or picked[x]} in ascending order, one
@@ -711,11 +868,19 @@ __global__ __launch_bounds__(COMPACT_TILE) void k_compact(BatchView bv) {
 
 hipError_t launch_niche(const HostPlan &hp, const BatchView &bv, hipStream_t s) {
     const unsigned pblocks = (unsigned)(hp.npt / 256);
+    const unsigned rblocks = (unsigned)(hp.nref / 4);
     if (!(bv.run & RUN_ASSOC))
         NSGA3_LAUNCH("niche_count", k_niche_count, dim3(pblocks), dim3(256), 0, s, bv);
-    NSGA3_LAUNCH("niche_plan", k_niche_plan, dim3(hp.B), dim3(PLAN_THREADS), 0, s, bv);
-    NSGA3_LAUNCH("niche_scatter", k_niche_scatter, dim3(pblocks), dim3(256), 0, s, bv);
-    NSGA3_LAUNCH("niche_pick", k_niche_pick, dim3((unsigned)(hp.nref / 4)), dim3(256), 0, s, bv);
+    if (bv.run & RUN_CACHE_TENSOR) {
+        NSGA3_LAUNCH("ct_offsets", k_ct_offsets, dim3(hp.B), dim3(PLAN_THREADS), 0, s, bv);
+        NSGA3_LAUNCH("niche_scatter", k_niche_scatter, dim3(pblocks), dim3(256), 0, s, bv);
+        NSGA3_LAUNCH("ct_order", k_niche_pick<true>, dim3(rblocks), dim3(256), 0, s, bv);
+        NSGA3_LAUNCH("ct_loop", k_ct_loop, dim3(hp.B), dim3(PLAN_THREADS), 0, s, bv);
+    } else {
+        NSGA3_LAUNCH("niche_plan", k_niche_plan, dim3(hp.B), dim3(PLAN_THREADS), 0, s, bv);
+        NSGA3_LAUNCH("niche_scatter", k_niche_scatter, dim3(pblocks), dim3(256), 0, s, bv);
+        NSGA3_LAUNCH("niche_pick", k_niche_pick<false>, dim3(rblocks), dim3(256), 0, s, bv);
+    }
     NSGA3_LAUNCH("compact", k_compact, dim3(hp.npt / 256), dim3(COMPACT_TILE), 0, s, bv);
     return hipGetLastError();
 }

@@ -36,6 +36,7 @@ enum : int {
     RUN_ASSOC = 4,
     RUN_NICHE = 8,
     RUN_SELECT = 15,
+    RUN_CACHE_TENSOR = 16,  // niche stage: the paper's cache-tensor loop instead of the closed form
 };
 
 // Objective counts up to NARROW_M run kernels specialized per m (values of
@@ -76,7 +77,7 @@ constexpr int TICKET_STRIDE = 32;   // u64 words between them (256 bytes)
 struct Layout {
     int M, m, H, N, Mp, W, Hp;
     size_t ctrl, ft, nd, mask, ring, list, fn, rank, pi, dist, akey, wn,
-        rho, cnt, off, fill, tpick, members, picked, tcnt, remain, emat, total;
+        rho, cnt, off, fill, tpick, members, qrow, picked, tcnt, remain, emat, total;
 };
 
 Layout make_layout(int M, int m, int H, int N);
@@ -94,6 +95,7 @@ struct Ptrs {
     u64 *akey;
     float *wn;
     int *rho, *cnt, *off, *fill, *tpick, *members, *picked;
+    int *qrow;          // cache-tensor baseline: candidates of each reference in pick order
     int *tcnt;          // selected points per compaction tile
     u64 *remain;
     double *emat;       // m > NARROW_M: the intercept system [m][m], rhs, column maxima, b

@@ -43,6 +43,7 @@ def lib():
     L.nsga3_normalize.argtypes = [P, P, P, i32, i32, P, P, P, P, P, P, sz, P]
     L.nsga3_associate.argtypes = [P, P, P, i32, i32, P, i32, P, P, P, sz, P]
     L.nsga3_niche.argtypes = [P, P, P, P, i32, i32, i32, u64, P, P, sz, P]
+    L.nsga3_niche_cache_tensor.argtypes = [P, P, P, P, i32, i32, i32, u64, P, P, sz, P]
     L.nsga3_select.argtypes = [P, i32, i32, P, i32, i32, u64, P, P, P, P, P, sz, P]
     L.nsga3_select_noalloc.argtypes = [P, i32, i32, P, i32, i32, u64, P, P, P, P, P, P]
     L.nsga3_read_status.argtypes = [P, P, P]
@@ -55,12 +56,18 @@ def lib():
     L.nsga3_evolve_workspace_bytes.argtypes = [i32]
     L.nsga3_evolve_workspace_bytes.restype = sz
     L.nsga3_evolve_batched.argtypes = [P, i32, P, sz, P]
+    L.nsga3_igd_workspace_bytes.argtypes = [i32]
+    L.nsga3_igd_workspace_bytes.restype = sz
+    L.nsga3_igd.argtypes = [P, i32, i32, P, i32, P, P, sz, P]
+    L.nsga3_hv_count.argtypes = [P, i32, i32, P, P, ctypes.c_int64, u64, P, P]
     L.nsga3_version.restype = ctypes.c_char_p
     L.nsga3_profile_enable.argtypes = [ctypes.c_char_p]
     L.nsga3_profile_read.argtypes = [ctypes.c_char_p, P, P, P]
     for f in ("nsga3_nd_sort", "nsga3_normalize", "nsga3_associate", "nsga3_niche",
+              "nsga3_niche_cache_tensor",
               "nsga3_select", "nsga3_select_noalloc", "nsga3_read_status", "nsga3_profile_enable", "nsga3_profile_read",
-              "nsga3_select_batched", "nsga3_read_status_batched", "nsga3_evolve_batched"):
+              "nsga3_select_batched", "nsga3_read_status_batched", "nsga3_evolve_batched",
+              "nsga3_igd", "nsga3_hv_count"):
         getattr(L, f).restype = i32
     _lib = L
     return L
@@ -177,8 +184,9 @@ def associate(Fn, rank, front_info, Z, ws=None):
     return pi, dist
 
 
-def niche(rank, front_info, pi, dist, H, N, seed, ws=None):
-    """Ascending selected indices int32[N]."""
+def niche(rank, front_info, pi, dist, H, N, seed, ws=None, cache_tensor=False):
+    """Ascending selected indices int32[N]. cache_tensor=True runs the paper's
+    cache-tensor loop (nsga3_niche_cache_tensor) instead of the closed form."""
     rank, front_info, pi = _i32(rank, "rank"), _i32(front_info, "front_info"), _i32(pi, "pi")
     if not (dist.is_cuda and dist.dtype == torch.float32):
         raise ValueError("dist must be a float32 CUDA tensor")
@@ -187,9 +195,10 @@ def niche(rank, front_info, pi, dist, H, N, seed, ws=None):
     ws = ws or Workspace(rank.device)
     buf = ws.get(workspace_bytes(M, 2, H, N))
     sel = torch.empty(int(N), dtype=torch.int32, device=rank.device)
-    _check(lib().nsga3_niche(_ptr(rank), _ptr(front_info), _ptr(pi), _ptr(dist), M, int(H), int(N),
-                             int(seed) & (2**64 - 1), _ptr(sel), _ptr(buf), buf.numel(),
-                             _stream(rank.device)), "nsga3_niche")
+    fn = lib().nsga3_niche_cache_tensor if cache_tensor else lib().nsga3_niche
+    _check(fn(_ptr(rank), _ptr(front_info), _ptr(pi), _ptr(dist), M, int(H), int(N),
+              int(seed) & (2**64 - 1), _ptr(sel), _ptr(buf), buf.numel(), _stream(rank.device)),
+           "nsga3_niche_cache_tensor" if cache_tensor else "nsga3_niche")
     return sel
 
 
@@ -216,6 +225,36 @@ def select(F, Z, N, seed, ws=None, out=None, intermediates=False):
     if intermediates:
         return dict(selected=sel, rank=rank, pi=pi, dist=dist)
     return sel
+
+
+def igd(F, R):
+    """IGD of the population F [n][m] against front points R [nr][m]
+    (float32 CUDA tensors): a float64 CUDA tensor of one element."""
+    F, R = _f32(F, "F", 2), _f32(R, "R", 2)
+    n, m = F.shape
+    nr = R.shape[0]
+    if R.shape[1] != m:
+        raise ValueError("R must have m columns")
+    ws = torch.empty(max(int(lib().nsga3_igd_workspace_bytes(nr)), 256), dtype=torch.uint8,
+                     device=F.device)
+    out = torch.empty(1, dtype=torch.float64, device=F.device)
+    _check(lib().nsga3_igd(_ptr(F), n, m, _ptr(R), nr, _ptr(out), _ptr(ws), ws.numel(),
+                           _stream(F.device)), "nsga3_igd")
+    return out
+
+
+def hv_count(F, ideal, ref, samples, seed):
+    """Number of the `samples` sample points of the box [ideal, ref] that the
+    population F [n][m] weakly dominates (an int64 CUDA tensor of one
+    element); count / samples is the normalized hypervolume."""
+    F = _f32(F, "F", 2)
+    n, m = F.shape
+    lo = (ctypes.c_float * m)(*[float(v) for v in ideal])
+    hi = (ctypes.c_float * m)(*[float(v) for v in ref])
+    out = torch.empty(1, dtype=torch.int64, device=F.device)
+    _check(lib().nsga3_hv_count(_ptr(F), n, m, lo, hi, int(samples), int(seed) & (2**64 - 1),
+                                _ptr(out), _stream(F.device)), "nsga3_hv_count")
+    return out
 
 
 NOALLOC_SCRATCH_BYTES = 64 << 20

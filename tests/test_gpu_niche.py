@@ -1,4 +1,5 @@
-"""GPU parity of nsga3_niche on pinned inputs: identical (rank, front_info,
+"""GPU parity of nsga3_niche (and of the cache-tensor baseline,
+nsga3_niche_cache_tensor) on pinned inputs: identical (rank, front_info,
 pi, dist) go to the GPU and to the oracle's sequential loop; the selected
 sets must be identical (integer result)."""
 import numpy as np
@@ -31,10 +32,14 @@ def make_case(rng, M, H, nfront, dist_ties=True):
 
 
 def check(rank, fi, pi, dist, H, N, seed, dev):
+    """The closed form (nsga3_niche) and the paper's cache-tensor loop
+    (nsga3_niche_cache_tensor) both equal the oracle's sequential loop."""
     ref = oracle.niche(rank, fi, pi, dist.astype(np.float64), H, N, seed)
-    sel = to_np(nsga3.niche(to_dev(rank, dev), to_dev(fi, dev), to_dev(pi, dev), to_dev(dist, dev),
-                            H, N, seed))
+    args = (to_dev(rank, dev), to_dev(fi, dev), to_dev(pi, dev), to_dev(dist, dev), H, N, seed)
+    sel = to_np(nsga3.niche(*args))
     assert np.array_equal(sel, ref)
+    ct = to_np(nsga3.niche(*args, cache_tensor=True))
+    assert np.array_equal(ct, ref), "cache-tensor loop differs from the oracle"
 
 
 @pytest.mark.parametrize("case", range(60))
