@@ -18,7 +18,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
 SOURCES = ["ndsort.hip", "normalize.hip", "associate.hip", "niche.hip", "evolve.hip", "quality.hip",
-           "api.hip"]
+           "tiny.hip", "api.hip"]
 
 FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",

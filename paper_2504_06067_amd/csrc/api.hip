@@ -435,6 +435,27 @@ static int run_select(std::vector<Spec> &v, void *ws, size_t ws_bytes, hipStream
     return to_status(enqueue(p, (char *)ws, s));
 }
 
+// A one-instance selection small enough for one workgroup: the same plan
+// and workspace (the status word and the internal outputs live where the
+// multi-kernel path puts them), one launch.
+static int run_select_tiny(std::vector<Spec> &v, void *ws, size_t ws_bytes, hipStream_t s) {
+    Plan p;
+    plan(v, nullptr, RUN_SELECT, p);
+    const int rc = check_ws(p.total, ws, ws_bytes);
+    if (rc) return rc;
+    place_select(p, v, (char *)ws);
+    plan(v, (char *)ws, RUN_SELECT, p);
+    Inst I0;
+    memcpy(&I0, p.hdr.data() + p.hl.tab, sizeof(Inst));
+    return to_status(launch_select_tiny(I0, s));
+}
+
+static int run_select_one(std::vector<Spec> &v, void *ws, size_t ws_bytes, hipStream_t s) {
+    const Inst &I = v[0].I;
+    if (tiny_fits(I.M, I.m, I.H)) return run_select_tiny(v, ws, ws_bytes, s);
+    return run_select(v, ws, ws_bytes, s);
+}
+
 static int status_code(int bits) {
     if (bits & ST_NONFINITE) return NSGA3_ENONFINITE;
     if (bits & ST_BADREF) return NSGA3_EINVAL;
@@ -639,7 +660,7 @@ int nsga3_select(const float *F, int32_t M, int32_t m, const float *Z, int32_t H
     if (!valid_instance(q)) return NSGA3_EINVAL;
     std::vector<Spec> v;
     specs_of(&q, 1, v);
-    return run_select(v, ws, ws_bytes, (hipStream_t)stream);
+    return run_select_one(v, ws, ws_bytes, (hipStream_t)stream);
 }
 
 int nsga3_select_noalloc(const float *F, int32_t M, int32_t m, const float *Z, int32_t H,
@@ -669,7 +690,7 @@ int nsga3_select_noalloc(const float *F, int32_t M, int32_t m, const float *Z, i
     char *ws = nullptr;
     if (scratch_of_current_device(&ws) != hipSuccess) return NSGA3_EHIP;
     hipStream_t s = (hipStream_t)stream;
-    const int rc = run_select(v, ws, NSGA3_NOALLOC_SCRATCH_BYTES, s);
+    const int rc = run_select_one(v, ws, NSGA3_NOALLOC_SCRATCH_BYTES, s);
     if (rc != NSGA3_OK || !status) return rc;
     // instance 0's control block sits at the start of the scratch
     NSGA3_LAUNCH("status", k_status_out, dim3(1), dim3(64), 0, s, (const Ctrl *)ws, status);

@@ -16,7 +16,7 @@
 //   k_associate    the fused sweep; slices merge by a 64-bit atomic min
 //   k_assoc_final  pi and dist from the merged keys; in a whole selection
 //                  also the niche counts rho (fronts < l) and c (front l)
-#include "nsga3_internal.h"
+#include "steps.h"
 
 namespace nsga3 {
 
@@ -39,24 +39,6 @@ __global__ __launch_bounds__(256) void k_assoc_list(BatchView bv) {
         I.P.list[base + mbcnt(bal)] = t;
         I.P.akey[t] = ~0ull;
     }
-}
-
-template <int MO>
-__device__ __forceinline__ void assoc_ref(const float (&f)[MO], const NSGA3_RO float *wn,
-                                          int Hp, int j, float &best, int &bj) {
-    float w[MO];
-#pragma unroll
-    for (int k = 0; k < MO; ++k) w[k] = wn[(size_t)k * Hp + j];
-    float p = f[0] * w[0];
-#pragma unroll
-    for (int k = 1; k < MO; ++k) p = fmaf(f[k], w[k], p);
-    float d2 = 0.0f;
-#pragma unroll
-    for (int k = 0; k < MO; ++k) {
-        const float r = fmaf(-p, w[k], f[k]);
-        d2 = fmaf(r, r, d2);
-    }
-    if (d2 < best) { best = d2; bj = j; }
 }
 
 // Merges a wave's best (d^2, reference) of its slice into the keys of its

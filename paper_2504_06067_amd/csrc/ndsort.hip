@@ -16,7 +16,7 @@
 //   k_peel       fronts of every instance, persistent over all their chunks
 #include <utility>
 
-#include "nsga3_internal.h"
+#include "steps.h"
 
 namespace nsga3 {
 
@@ -119,15 +119,6 @@ __global__ __launch_bounds__(256) void k_prep(BatchView bv, int npt) {
         }
         if (ballot(bad) != 0 && lane_id() == 0) atomicOr(&I.P.ctrl->status, ST_BADREF);
     }
-}
-
-// (a << 1) | bit(lane) for every lane, with the bits taken from a wave mask:
-// one v_addc with the mask as carry-in (a + a + carry).
-__device__ __forceinline__ unsigned shift_in(unsigned a, u64 mask) {
-    unsigned r;
-    u64 carry_out;
-    asm("v_addc_co_u32 %0, %1, %2, %2, %3" : "=v"(r), "=s"(carry_out) : "v"(a), "s"(mask));
-    return r;
 }
 
 // Lane R of `old` takes the wave-uniform value v.

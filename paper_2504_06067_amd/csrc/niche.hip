@@ -28,7 +28,7 @@
 //   k_ct_offsets, k_ct_loop   the paper's cache-tensor loop (A/B baseline)
 #include <limits.h>
 
-#include "nsga3_internal.h"
+#include "steps.h"
 
 namespace nsga3 {
 
@@ -783,14 +783,13 @@ __device__ void ct_loop(CInst &I, int *lev, int *left) {
                     if ((key & pmask) == prefix) atomicAdd(&hist[(key >> shift) & 255u], 1u);
                 }
                 lds_barrier();
-                if (tid == 0) {
-                    int acc = 0, d = 255;
-                    for (int q = 0; q < 256; ++q) {
-                        if (acc + (int)hist[q] >= need) { d = q; break; }
-                        acc += (int)hist[q];
+                if (tid < 64) {
+                    int d, rest;
+                    hist_digit(hist, need, d, rest);
+                    if (tid == 0) {
+                        s_sel[0] = d;
+                        s_sel[1] = rest;
                     }
-                    s_sel[0] = d;
-                    s_sel[1] = need - acc;
                 }
                 lds_barrier();
                 prefix |= (u64)uniform(s_sel[0]) << shift;

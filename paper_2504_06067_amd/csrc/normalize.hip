@@ -15,7 +15,7 @@
 //                   tests)
 //   k_norm_apply    Fn = (f - z) * (1 / a) over S_t (stage call; a whole
 //                   selection forms Fn in the association sweep)
-#include "nsga3_internal.h"
+#include "steps.h"
 
 namespace nsga3 {
 
@@ -67,120 +67,6 @@ __global__ __launch_bounds__(256) void k_norm_reduce(BatchView bv, int wide_only
     int off = uniform(s_base);
     for (int v = 0; v < wv; ++v) off += s_cnt[v];
     if (in) I.P.list[off + mbcnt(bal)] = x;
-}
-
-// Doubles move between lanes as two 32-bit halves.
-__device__ __forceinline__ double read_lane_f64(double v, int L) {
-    const u64 u = (u64)__double_as_longlong(v);
-    const unsigned lo = __builtin_amdgcn_readlane((unsigned)u, L);
-    const unsigned hi = __builtin_amdgcn_readlane((unsigned)(u >> 32), L);
-    return __longlong_as_double((long long)(((u64)hi << 32) | lo));
-}
-
-// One wave per instance. E[k][j] =
-// f(e_k)_j - z_j in FP64; E b = 1 is solved by Gaussian elimination with
-// partial pivoting (largest |pivot|, least row on ties), the rows spread over
-// the lanes (each row stays in its lane and carries its position; a swap
-// exchanges two positions), every product and difference rounded separately;
-// a_k = 1 / b_k
-// unless degenerate.
-template <int MO>
-__device__ void norm_solve(CInst &I) {
-    Ctrl *ctrl = I.P.ctrl;
-    const int lane = lane_id();
-    const int M = I.M;
-    // ideal point, extreme indices, per-objective span (lane k: objective k)
-    int bad = 0;
-    double zk = 0.0, fmxk = 0.0;
-    int ek = 0;
-    if (lane < MO) {
-        const float zf = ord2f(ctrl->zmin_enc[lane]);
-        zk = (double)zf;
-        fmxk = (double)ord2f(ctrl->fmax_enc[lane]) - zk;
-        ek = (int)(unsigned)(ctrl->ext_key[lane] & 0xffffffffull);
-        if (ek < 0 || ek >= M) { ek = 0; bad = 1; }
-        ctrl->zf[lane] = zf;
-        I.ideal[lane] = zf;
-        I.extreme[lane] = ek;
-    }
-    int degen = uniform((int)(ballot(bad != 0) != 0));
-    if (degen && lane == 0) atomicOr(&ctrl->status, ST_INTERNAL);
-    // row i of E in lane i: A[j] = f(e_i)_j - z_j, right-hand side 1
-    double A[MO];
-    double rhs = 1.0;
-#pragma unroll
-    for (int j = 0; j < MO; ++j) {
-        const double zj = read_lane_f64(zk, j);
-        A[j] = lane < MO ? (double)I.F[(size_t)ek * MO + j] - zj : 0.0;
-    }
-    // largest |entry| per column of the original matrix
-    double colmax[MO];
-#pragma unroll
-    for (int j = 0; j < MO; ++j) {
-        const u64 key = lane < MO ? (u64)__double_as_longlong(fabs(A[j])) : 0ull;
-        colmax[j] = __longlong_as_double((long long)wave_max_u64(key));
-    }
-    // Rows stay in their lanes; pos is the row's position in the eliminated
-    // matrix (a swap of two positions exchanges two lanes' pos values).
-    int pos = lane;
-#pragma unroll
-    for (int c = 0; c < MO; ++c) {
-        if (degen) break;
-        // pivot: largest |A[i][c]| over positions i >= c, least position on ties
-        const bool cand = lane < MO && pos >= c;
-        const u64 key = cand ? (u64)__double_as_longlong(fabs(A[c])) : 0ull;
-        const u64 best = wave_max_u64(key);
-        const int piv = (int)wave_min_u32(cand && key == best ? (unsigned)pos : 0xffffffffu);
-        const double pv = __longlong_as_double((long long)best);
-        if (colmax[c] == 0.0 || pv < 1e-10 * colmax[c]) {
-            degen = 1;
-            break;
-        }
-        const int lp = __ffsll((long long)ballot(lane < MO && pos == piv)) - 1;  // pivot row's lane
-        const int lc = __ffsll((long long)ballot(lane < MO && pos == c)) - 1;    // position c's lane
-        if (piv != c) {
-            if (lane == lp) pos = c;
-            else if (lane == lc) pos = piv;
-        }
-        const double acc = read_lane_f64(A[c], lp);
-        const double rc = read_lane_f64(rhs, lp);
-        const bool below = lane < MO && pos > c;
-        const double f = below ? A[c] / acc : 0.0;
-#pragma unroll
-        for (int j = c; j < MO; ++j) {
-            const double acj = read_lane_f64(A[j], lp);
-            if (below) A[j] = __dsub_rn(A[j], __dmul_rn(f, acj));
-        }
-        if (below) rhs = __dsub_rn(rhs, __dmul_rn(f, rc));
-    }
-    double b[MO];
-    if (!degen) {
-#pragma unroll
-        for (int i = MO - 1; i >= 0; --i) {
-            const int li = __ffsll((long long)ballot(lane < MO && pos == i)) - 1;  // row at position i
-            double s = read_lane_f64(rhs, li);
-#pragma unroll
-            for (int j = i + 1; j < MO; ++j) s = __dsub_rn(s, __dmul_rn(read_lane_f64(A[j], li), b[j]));
-            b[i] = s / read_lane_f64(A[i], li);
-        }
-    }
-    // intercepts, or the per-objective maximum when degenerate
-    double ak = 1.0;
-#pragma unroll
-    for (int k = 0; k < MO; ++k) {
-        if (degen) break;
-        const double fk = read_lane_f64(fmxk, k);
-        if (!(b[k] > 0.0)) { degen = 1; break; }
-        const double a = 1.0 / b[k];
-        if (!isfinite(a) || a < 1e-6 * fk) { degen = 1; break; }
-        if (k == lane) ak = a;
-    }
-    if (degen) ak = fmxk > 0.0 ? fmxk : 1.0;
-    if (lane < MO) {
-        I.intercept[lane] = ak;
-        ctrl->recip[lane] = (float)(1.0 / ak);
-    }
-    if (lane == 0) *I.degenerate = degen;
 }
 
 // ASF_k(x) = max(f'_k, max_{j != k} 1e6 * f'_j) with f' = f - z >= 0 on S_t,
@@ -250,7 +136,7 @@ __global__ __launch_bounds__(256) void k_norm_extreme(BatchView bv, int gs, int 
     lds_barrier();
     if (s_last && threadIdx.x < 64) {
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        norm_solve<MO>(I);
+        norm_solve<MO>(I, ctrl->zmin_enc, ctrl->fmax_enc, ctrl->ext_key, I.F, ctrl->zf, ctrl->recip);
     }
 }
 
@@ -340,7 +226,7 @@ __global__ __launch_bounds__(256) void k_norm_fused(BatchView bv) {
     lds_barrier();
     if (s_last && threadIdx.x < 64) {
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        norm_solve<MO>(I);
+        norm_solve<MO>(I, ctrl->zmin_enc, ctrl->fmax_enc, ctrl->ext_key, I.F, ctrl->zf, ctrl->recip);
     }
 }
 

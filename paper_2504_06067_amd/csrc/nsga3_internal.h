@@ -403,6 +403,11 @@ hipError_t launch_normalize(const HostPlan &hp, const BatchView &bv, hipStream_t
 hipError_t launch_associate(const HostPlan &hp, const BatchView &bv, hipStream_t s);
 hipError_t launch_niche(const HostPlan &hp, const BatchView &bv, hipStream_t s);
 
+// One-workgroup selection of a small instance (tiny.hip): whether the shape
+// qualifies, and the launch (I: the planned descriptor of the instance).
+bool tiny_fits(int M, int m, int H);
+hipError_t launch_select_tiny(const Inst &I, hipStream_t s);
+
 // dominance work items of an instance (waves): block row jb holds
 // floor(jb / G) + 1 items of up to G column tiles each
 long long dominance_tiles(int W);  // 64x64 tiles of the triangle ib <= jb
