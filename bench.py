@@ -56,6 +56,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batched-reps", type=int, default=20)
+    ap.add_argument("--batched-no-plain", action="store_true",
+                    help="batched leg: graph replays only (no plain comparison), for profiling")
     ap.add_argument("--only-batched", action="store_true",
                     help="run the batched comparison alone (for profiling it separately)")
     ap.add_argument("--no-served", action="store_true")
@@ -262,6 +264,9 @@ def bench_batched(args, dev):
     if bt.status() != [nsga3.OK] * len(insts):
         raise RuntimeError("batched status not OK")
     g_med, g_p99 = _median_ms(graph.replay, args.batched_reps, stream)
+    if args.batched_no_plain:
+        # graph replays only (for a kernel trace of the batched call alone)
+        return {"graph_ms": {"p50": g_med, "p99": g_p99}, "value": total / (g_med / 1e3)}
     e_med, _ = _median_ms(bt.run, args.batched_reps, stream)
 
     wss = [nsga3.Workspace(dev) for _ in probs]

@@ -455,36 +455,51 @@ __device__ __forceinline__ void wave_sync() {
 }
 
 // Ascending bitonic sort of buf[0..n) by one wave; positions >= n act as +inf
-// (the "flip then half-clean" form needs no explicit padding).
+// (the "flip then half-clean" form needs no explicit padding). Block sizes
+// are powers of two, so block and position come from shifts and masks; the
+// compare-exchanges of one stage are independent, and up to four per lane
+// are loaded before any is stored.
 __device__ void wave_sort(int *buf, int n) {
     const int lane = lane_id();
-    int np = 1;
-    while (np < n) np <<= 1;
-    for (int size = 2; size <= np; size <<= 1) {
-        // flip: compare i with the mirror partner in its block of `size`
-        for (int i = lane; i < np / 2; i += 64) {
-            const int blk = i / (size / 2);
-            const int pos = i % (size / 2);
-            const int a = blk * size + pos;
-            const int b = blk * size + size - 1 - pos;
-            if (b < n) {
-                const int va = buf[a], vb = buf[b];
-                if (va > vb) { buf[a] = vb; buf[b] = va; }
+    int lp = 0;
+    while ((1 << lp) < n) ++lp;
+    const int half_n = (1 << lp) >> 1;  // compare-exchanges per stage
+    auto stage = [&](auto pair_of) {
+        for (int i0 = lane; i0 < half_n; i0 += 256) {
+            int a[4], b[4], va[4], vb[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int i = i0 + 64 * q;
+                pair_of(i, a[q], b[q]);
+                const bool ok = i < half_n && b[q] < n;
+                va[q] = ok ? buf[a[q]] : 0;
+                vb[q] = ok ? buf[b[q]] : 0;
+                if (!ok) b[q] = -1;
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                if (b[q] >= 0 && va[q] > vb[q]) {
+                    buf[a[q]] = vb[q];
+                    buf[b[q]] = va[q];
+                }
             }
         }
         wave_sync();
-        for (int half = size / 4; half >= 1; half >>= 1) {
-            for (int i = lane; i < np / 2; i += 64) {
-                const int blk = i / half;
-                const int pos = i % half;
-                const int a = blk * 2 * half + pos;
-                const int b = a + half;
-                if (b < n) {
-                    const int va = buf[a], vb = buf[b];
-                    if (va > vb) { buf[a] = vb; buf[b] = va; }
-                }
-            }
-            wave_sync();
+    };
+    for (int ls = 1; ls <= lp; ++ls) {
+        // flip: i against the mirror partner in its block of 2^ls
+        const int hs = ls - 1;
+        stage([&](int i, int &a, int &b) {
+            const int blk = i >> hs, pos = i & ((1 << hs) - 1);
+            a = (blk << ls) + pos;
+            b = (blk << ls) + (1 << ls) - 1 - pos;
+        });
+        for (int lh = ls - 2; lh >= 0; --lh) {
+            stage([&](int i, int &a, int &b) {
+                const int blk = i >> lh, pos = i & ((1 << lh) - 1);
+                a = (blk << (lh + 1)) + pos;
+                b = a + (1 << lh);
+            });
         }
     }
 }
@@ -508,6 +523,134 @@ __device__ __forceinline__ int select_bit(u64 w, int k) {
 // picked, level after level, and the picks are written in that order to its
 // row of the cache tensor (qrow, the reference's segment of the CSR) instead
 // of being marked selected.
+// Sorts a reference's candidate segment ascending, then makes its picks at
+// levels rj .. rj + t - 1. buf and rem are the segment and its remaining-set
+// words, either in LDS or in global memory: each call site passes pointers
+// of one kind, so that after inlining every access has a known address space
+// (no flat accesses).
+template <bool ORDER>
+__device__ __forceinline__ void pick_sorted(int *buf, u64 *rem, int c, int t, int rj, int j,
+                                            u64 seed, const float *__restrict__ dist,
+                                            int *picked, int *tcnt, int *qrow) {
+    const int lane = lane_id();
+    int emitted = 0;  // ORDER: picks written so far
+    // records pick x (lane 0)
+    auto emit = [&](int x) {
+        if (ORDER) {
+            qrow[emitted++] = x;
+        } else {
+            picked[x] = 1;
+            atomicAdd(&tcnt[x / COMPACT_TILE], 1);
+        }
+    };
+    wave_sort(buf, c);
+    const int nw = (c + 63) / 64;
+    if (nw <= 64) {
+        // Up to 4096 candidates: lane w holds word w of the remaining set in a
+        // register, and the pick ranks of 64 levels at a time are computed one
+        // per lane (they depend on the level only).
+        const int v0 = c - lane * 64;
+        u64 myrem = lane < nw ? (v0 >= 64 ? ~0ull : ((1ull << v0) - 1)) : 0ull;
+        int own = __popcll(myrem);
+        // exclusive prefix of the remaining counts by lane, kept current
+        // after every removal (no scan per pick)
+        int excl = wave_incl_scan(own) - own;
+        int kk_lane = 0, kk_base = -1;
+        for (int lev = rj; lev < rj + t; ++lev) {
+            int pos;
+            if (lev == 0) {
+                // first pick of a reference at niche count 0: the nearest candidate
+                u64 best = ~0ull;
+#pragma unroll 4
+                for (int i = lane; i < c; i += 64) {
+                    const int x = buf[i];
+                    const u64 k = ((u64)__float_as_uint(dist[x]) << 32) | (unsigned)i;
+                    best = k < best ? k : best;
+                }
+                best = wave_min_u64(best);
+                pos = (int)(unsigned)(best & 0xffffffffull);
+            } else {
+                if (kk_base < 0 || lev - kk_base >= 64) {
+                    kk_base = lev;
+                    const int lv = lev + lane;
+                    kk_lane = lv < rj + t ? (int)(tie_key(seed, 2u, (unsigned)j, (unsigned)lv) %
+                                                  (u64)(c - (lv - rj)))
+                                          : 0;
+                }
+                const int kk = __builtin_amdgcn_readlane(kk_lane, lev - kk_base);
+                const u64 owner = ballot(excl <= kk && kk < excl + own);
+                if (owner == 0) break;  // unreachable while the counts are consistent
+                const int L = __ffsll((long long)owner) - 1;
+                // the word and its prefix on the owning lane, the bit on the
+                // scalar unit
+                const u64 w = ((u64)(unsigned)__builtin_amdgcn_readlane((int)(myrem >> 32), L) << 32) |
+                              (unsigned)__builtin_amdgcn_readlane((int)myrem, L);
+                const int base = __builtin_amdgcn_readlane(excl, L);
+                pos = L * 64 + select_bit(w, kk - base);
+            }
+            if (pos < 0 || pos >= c) break;
+            // remove position pos: its word's lane loses one, later lanes'
+            // prefixes drop by one
+            const int lw = pos >> 6;
+            if (lane == lw) {
+                myrem &= ~(1ull << (pos & 63));
+                own -= 1;
+            }
+            if (lane > lw) excl -= 1;
+            if (lane == 0) emit(buf[pos]);
+        }
+        return;
+    }
+    for (int w = lane; w < nw; w += 64) {
+        const int v = c - w * 64;
+        rem[w] = v >= 64 ? ~0ull : ((1ull << v) - 1);
+    }
+    // lane L owns words [L*s, (L+1)*s) and keeps their population count
+    const int s = (nw + 63) / 64;
+    int own = 0;
+    for (int w = lane * s; w < min(nw, (lane + 1) * s); ++w) own += __popcll(rem[w]);
+    wave_sync();
+    for (int lev = rj; lev < rj + t; ++lev) {
+        const int remaining = c - (lev - rj);
+        int pos;
+        if (lev == 0) {
+            // first pick of a reference at niche count 0: the nearest candidate
+            u64 best = ~0ull;
+#pragma unroll 4
+            for (int i = lane; i < c; i += 64) {
+                const int x = buf[i];
+                const u64 k = ((u64)__float_as_uint(dist[x]) << 32) | (unsigned)i;
+                best = k < best ? k : best;
+            }
+            best = wave_min_u64(best);
+            pos = (int)(unsigned)(best & 0xffffffffull);
+        } else {
+            const int kk = (int)(tie_key(seed, 2u, (unsigned)j, (unsigned)lev) % (u64)remaining);
+            const int incl = wave_incl_scan(own);
+            const int excl = incl - own;
+            const u64 owner = ballot(excl <= kk && kk < incl);
+            if (owner == 0) break;  // unreachable while the counts are consistent
+            const int L = __ffsll((long long)owner) - 1;
+            int found = 0;
+            if (lane == L) {
+                int k2 = kk - excl;
+                for (int w = lane * s; w < min(nw, (lane + 1) * s); ++w) {
+                    const int pc = __popcll(rem[w]);
+                    if (k2 < pc) { found = w * 64 + select_bit(rem[w], k2); break; }
+                    k2 -= pc;
+                }
+            }
+            pos = __builtin_amdgcn_readlane(found, L);
+        }
+        if (pos < 0 || pos >= c) break;
+        // remove position pos
+        if (lane == 0) rem[pos >> 6] &= ~(1ull << (pos & 63));
+        if (lane == (pos >> 6) / s) own -= 1;
+        if (lane == 0) emit(buf[pos]);
+        wave_sync();
+    }
+}
+
 template <bool ORDER>
 __global__ __launch_bounds__(256) void k_niche_pick(BatchView bv) {
     __shared__ int s_buf[4][PICK_CAP];
@@ -565,112 +708,14 @@ __global__ __launch_bounds__(256) void k_niche_pick(BatchView bv) {
         if (lane == 0) emit((int)(unsigned)(best & 0xffffffffull));
         return;
     }
-    int *buf;
-    u64 *rem;
     if (c <= PICK_CAP) {
-        buf = s_buf[wv];
-        rem = s_rem[wv];
-        for (int i = lane; i < c; i += 64) buf[i] = seg[i];
+#pragma unroll 8
+        for (int i = lane; i < c; i += 64) s_buf[wv][i] = seg[i];
         wave_sync();
+        pick_sorted<ORDER>(s_buf[wv], s_rem[wv], c, t, rj, j, seed, dist, picked, tcnt, qrow);
     } else {
-        buf = seg;
-        rem = remain_g + (off[j] >> 6) + j;
-    }
-    wave_sort(buf, c);
-    const int nw = (c + 63) / 64;
-    if (nw <= 64) {
-        // Up to 4096 candidates: lane w holds word w of the remaining set in a
-        // register, and the pick ranks of 64 levels at a time are computed one
-        // per lane (they depend on the level only).
-        const int v0 = c - lane * 64;
-        u64 myrem = lane < nw ? (v0 >= 64 ? ~0ull : ((1ull << v0) - 1)) : 0ull;
-        int own = __popcll(myrem);
-        int kk_lane = 0, kk_base = -1;
-        for (int lev = rj; lev < rj + t; ++lev) {
-            int pos;
-            if (lev == 0) {
-                // first pick of a reference at niche count 0: the nearest candidate
-                u64 best = ~0ull;
-                for (int i = lane; i < c; i += 64) {
-                    const int x = buf[i];
-                    const u64 k = ((u64)__float_as_uint(dist[x]) << 32) | (unsigned)i;
-                    best = k < best ? k : best;
-                }
-                best = wave_min_u64(best);
-                pos = (int)(unsigned)(best & 0xffffffffull);
-            } else {
-                if (kk_base < 0 || lev - kk_base >= 64) {
-                    kk_base = lev;
-                    const int lv = lev + lane;
-                    kk_lane = lv < rj + t ? (int)(tie_key(seed, 2u, (unsigned)j, (unsigned)lv) %
-                                                  (u64)(c - (lv - rj)))
-                                          : 0;
-                }
-                const int kk = __builtin_amdgcn_readlane(kk_lane, lev - kk_base);
-                const int incl = wave_incl_scan(own);
-                const int excl = incl - own;
-                const u64 owner = ballot(excl <= kk && kk < incl);
-                if (owner == 0) break;  // unreachable while the counts are consistent
-                const int L = __ffsll((long long)owner) - 1;
-                const int found = lane * 64 + select_bit(myrem, kk - excl);  // meaningful on lane L
-                pos = __builtin_amdgcn_readlane(found, L);
-            }
-            if (pos < 0 || pos >= c) break;
-            // remove position pos
-            if (lane == (pos >> 6)) {
-                myrem &= ~(1ull << (pos & 63));
-                own -= 1;
-            }
-            if (lane == 0) emit(buf[pos]);
-        }
-        return;
-    }
-    for (int w = lane; w < nw; w += 64) {
-        const int v = c - w * 64;
-        rem[w] = v >= 64 ? ~0ull : ((1ull << v) - 1);
-    }
-    // lane L owns words [L*s, (L+1)*s) and keeps their population count
-    const int s = (nw + 63) / 64;
-    int own = 0;
-    for (int w = lane * s; w < min(nw, (lane + 1) * s); ++w) own += __popcll(rem[w]);
-    wave_sync();
-    for (int lev = rj; lev < rj + t; ++lev) {
-        const int remaining = c - (lev - rj);
-        int pos;
-        if (lev == 0) {
-            // first pick of a reference at niche count 0: the nearest candidate
-            u64 best = ~0ull;
-            for (int i = lane; i < c; i += 64) {
-                const int x = buf[i];
-                const u64 k = ((u64)__float_as_uint(dist[x]) << 32) | (unsigned)i;
-                best = k < best ? k : best;
-            }
-            best = wave_min_u64(best);
-            pos = (int)(unsigned)(best & 0xffffffffull);
-        } else {
-            const int kk = (int)(tie_key(seed, 2u, (unsigned)j, (unsigned)lev) % (u64)remaining);
-            const int incl = wave_incl_scan(own);
-            const int excl = incl - own;
-            const u64 owner = ballot(excl <= kk && kk < incl);
-            if (owner == 0) break;  // unreachable while the counts are consistent
-            const int L = __ffsll((long long)owner) - 1;
-            int found = 0;
-            if (lane == L) {
-                int k2 = kk - excl;
-                for (int w = lane * s; w < min(nw, (lane + 1) * s); ++w) {
-                    const int pc = __popcll(rem[w]);
-                    if (k2 < pc) { found = w * 64 + select_bit(rem[w], k2); break; }
-                    k2 -= pc;
-                }
-            }
-            pos = __builtin_amdgcn_readlane(found, L);
-        }
-        if (pos < 0 || pos >= c) break;
-        // remove position pos
-        if (lane == 0) rem[pos >> 6] &= ~(1ull << (pos & 63));
-        if (lane == (pos >> 6) / s) own -= 1;
-        if (lane == 0) emit(buf[pos]);
-        wave_sync();
+        pick_sorted<ORDER>(seg, remain_g + (off[j] >> 6) + j, c, t, rj, j, seed, dist, picked,
+                           tcnt, qrow);
     }
 }
 
