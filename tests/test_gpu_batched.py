@@ -92,6 +92,12 @@ def test_tile_invariance():
         got = run_batched(insts, dev, tiles)
         for a, b in zip(base, got):
             assert same(a, b), (g_tile, r_tile)
+    # the autotuned table's tiles (dominance items and association slices)
+    from paper_2504_06067_amd import autotune
+    tuned = [autotune.lookup(q["M"], q["m"], q["H"]) for q in insts]
+    got = run_batched(insts, dev, tuned)
+    for a, b in zip(base, got):
+        assert same(a, b), "tuned tiles"
 
 
 def test_alone_equals_in_mix():
