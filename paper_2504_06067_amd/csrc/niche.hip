@@ -341,6 +341,22 @@ __global__ __launch_bounds__(PLAN_THREADS) void k_niche_plan(BatchView bv) {
         u64 pmask = 0;
         int need = r;
         int left = (int)tsize;  // keys matching the prefix
+        if (listed && ntk <= PLAN_THREADS) {
+            // few keys: each key's rank is the number of smaller ones (keys
+            // of distinct references differ); the one of rank r - 1 is the
+            // threshold, found in one pass instead of radix passes
+            if (tid < ntk) {
+                const u64 mine = t_key[tid];
+                int rank = 0;
+#pragma unroll 8
+                for (int v = 0; v < ntk; ++v) rank += t_key[v] < mine;
+                if (rank == r - 1) cand_thr[0] = mine;
+            }
+            lds_barrier();
+            prefix = uniform(cand_thr[0]);
+            pmask = ~0ull;
+            left = 0;
+        }
         for (int shift = 52; left > 64; shift = shift >= 12 ? shift - 12 : 0) {
             const int bits = shift >= 4 ? 12 : 4;
             const unsigned dmask = (1u << bits) - 1u;
