@@ -33,6 +33,11 @@ Layout make_layout(int M, int m, int H, int N) {
     L.nd = take(Mp * 4);
     L.mask = take(W * Mp * 8);
     L.ring = take((size_t)PEEL_RING * front_slot_words(L.W) * 8);  // peel front ring
+    L.perm = take(Mp * 4);
+    L.pkey = take(Mp * 4);
+    L.bcount = take((size_t)PLACE_BUCKETS * 4);
+    L.row_ord = take(W * 4);
+    L.col_end = take(W * 4);
     L.list = take(Mp * 4);
     L.fn = take(Mp * (size_t)m * 4);
     L.rank = take(Mp * 4);
@@ -63,6 +68,11 @@ Ptrs carve(const Layout &L, void *ws) {
     P.nd = (int *)(b + L.nd);
     P.mask = (u64 *)(b + L.mask);
     P.ring = (u64 *)(b + L.ring);
+    P.perm = (int *)(b + L.perm);
+    P.pkey = (unsigned *)(b + L.pkey);
+    P.bcount = (unsigned *)(b + L.bcount);
+    P.row_ord = (int *)(b + L.row_ord);
+    P.col_end = (int *)(b + L.col_end);
     P.list = (int *)(b + L.list);
     P.fn = (float *)(b + L.fn);
     P.rank = (int *)(b + L.rank);
@@ -244,7 +254,6 @@ static void plan(std::vector<Spec> &spec, char *ws, int run, Plan &p) {
         tab[b] = I;
         pt[b + 1] = pt[b] + (int)((I.M + PT_ALIGN - 1) / PT_ALIGN * PT_ALIGN);
         ref[b + 1] = ref[b] + (int)((I.Hp + PT_ALIGN - 1) / PT_ALIGN * PT_ALIGN);
-        chunk[b + 1] = chunk[b] + I.W;
         order[b] = b;
     }
     std::stable_sort(order.begin(), order.end(),
@@ -253,19 +262,25 @@ static void plan(std::vector<Spec> &spec, char *ws, int run, Plan &p) {
     hp.B = B;
     hp.npt = pt[B];
     hp.nref = ref[B];
-    hp.nchunk = chunk[B];
     hp.ngroups = 0;
     hp.max_W = 0;
     for (int i = 0; i < B; ++i) {
         const Inst &I = tab[order[i]];
+        chunk[i + 1] = chunk[i] + I.W;
         if (I.W > hp.max_W) hp.max_W = I.W;
         if (i == 0 || I.m != tab[order[i - 1]].m) {
             hp.grp_m[hp.ngroups] = I.m;
             hp.grp_start[hp.ngroups] = i;
+            hp.grp_chunk[hp.ngroups] = chunk[i];
+            hp.grp_max_W[hp.ngroups] = 0;
             ++hp.ngroups;
         }
+        int &gw = hp.grp_max_W[hp.ngroups - 1];
+        if (I.W > gw) gw = I.W;
     }
+    hp.nchunk = chunk[B];
     hp.grp_start[hp.ngroups] = B;
+    hp.grp_chunk[hp.ngroups] = chunk[B];
     const long long dom_waves = DOM_WAVES_PER_CU * device_info().cus;
     for (int g = 0; g < hp.ngroups; ++g) {
         long long tiles = 0;

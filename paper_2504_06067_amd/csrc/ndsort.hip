@@ -14,6 +14,7 @@
 //   k_dominance  triangle of 64x64 tiles; both directions from one set of 2m
 //                compares per pair; fused dominator counts
 //   k_peel       fronts of every instance, persistent over all their chunks
+#include <mutex>
 #include <utility>
 
 #include "steps.h"
@@ -25,7 +26,9 @@ long long dominance_tiles(int W) { return (long long)W * (W + 1) / 2; }
 __global__ __launch_bounds__(256) void k_init(BatchView bv) {
     CInst &I = bv.tab[blockIdx.x];
     init_instance(I.P.ctrl, I.front_info, I.n_stop, bv.run, threadIdx.x);
-    if (blockIdx.x == 0 && threadIdx.x < TICKET_SHARDS) bv.ticket[threadIdx.x * TICKET_STRIDE] = 0;
+    static_assert(TICKET_SHARDS * PEEL_PIPE_GROUPS <= 256, "one word per thread");
+    if (blockIdx.x == 0 && threadIdx.x < TICKET_SHARDS * PEEL_PIPE_GROUPS)
+        bv.ticket[(threadIdx.x % TICKET_SHARDS) * TICKET_STRIDE + threadIdx.x / TICKET_SHARDS] = 0;
 }
 
 // Grid: [all instances' padded points][all instances' padded references].
@@ -43,20 +46,30 @@ __global__ __launch_bounds__(256) void k_prep(BatchView bv, int npt) {
         // same float. Reduced per wave, then per block in LDS: one atomic
         // per block and objective (atomics on one address serialize).
         const bool ideal_here = (bv.run & RUN_ND) && (bv.run & RUN_NORM) && m <= NARROW_M;
-        __shared__ unsigned s_lo[4][NARROW_M];
+        // objective k of the wave's points reduced to its least value (the
+        // ideal point) and, for k = 0, also to its largest (the range of the
+        // placement buckets); slot NARROW_M holds the largest first objective
+        __shared__ unsigned s_lo[4][NARROW_M + 1];
         const int wv = threadIdx.x >> 6;
-        if (ideal_here && lane_id() < m) s_lo[wv][lane_id()] = 0xffffffffu;
+        if ((bv.run & RUN_ND) && lane_id() <= NARROW_M)
+            s_lo[wv][lane_id()] = lane_id() == NARROW_M ? 0u : 0xffffffffu;
         if (j < Mp && (bv.run & RUN_ND)) {
             for (int k = 0; k < m; ++k) {
                 float v = INFINITY;
                 if (j < M) {
                     v = I.F[(size_t)j * m + k];
                     bad |= !isfinite(v);
+                } else {
+                    // padding positions (the placement fills positions < M)
+                    I.P.ft[((size_t)(j >> 6) * m + k) * 64 + (j & 63)] = v;
                 }
-                I.P.ft[((size_t)(j >> 6) * m + k) * 64 + (j & 63)] = v;
-                if (ideal_here) {
+                if (ideal_here || k == 0) {
                     const unsigned lo = wave_min_u32(j < M ? f2ord(v) : 0xffffffffu);
                     if (lane_id() == 0) s_lo[wv][k] = lo;
+                }
+                if (k == 0) {
+                    const unsigned hi = wave_max_u32(j < M ? f2ord(v) : 0u);
+                    if (lane_id() == 0) s_lo[wv][NARROW_M] = hi;
                 }
             }
             I.P.nd[j] = 0;
@@ -72,13 +85,26 @@ __global__ __launch_bounds__(256) void k_prep(BatchView bv, int npt) {
                 }
             }
         }
-        if (ideal_here) {
-            // ideal_here and the points branch are uniform over the block
+        // every instance's point range starts with a whole block (PT_ALIGN)
+        static_assert(PLACE_BUCKETS <= 4 * PT_ALIGN, "four bucket counts per thread");
+        if ((bv.run & RUN_ND) && j < PLACE_BUCKETS / 4) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) I.P.bcount[4 * j + q] = 0;
+        }
+        if (bv.run & RUN_ND) {
+            // the run flags and the points branch are uniform over the block
             lds_barrier();
-            if ((int)threadIdx.x < m) {
-                const int k = threadIdx.x;
+            const int k = threadIdx.x;
+            if (k < (ideal_here ? m : 1)) {
                 const unsigned lo = min(min(s_lo[0][k], s_lo[1][k]), min(s_lo[2][k], s_lo[3][k]));
-                if (lo != 0xffffffffu) atomicMin(&I.P.ctrl->zmin_enc[k], lo);
+                if (lo != 0xffffffffu) {
+                    if (ideal_here) atomicMin(&I.P.ctrl->zmin_enc[k], lo);
+                    if (k == 0) atomicMin(&I.P.ctrl->f1_lo, lo);
+                }
+            } else if (k == 64) {
+                const unsigned hi = max(max(s_lo[0][NARROW_M], s_lo[1][NARROW_M]),
+                                        max(s_lo[2][NARROW_M], s_lo[3][NARROW_M]));
+                if (hi != 0u) atomicMax(&I.P.ctrl->f1_hi, hi);
             }
         }
         if (j < M && (bv.run & RUN_NICHE)) {
@@ -118,6 +144,111 @@ __global__ __launch_bounds__(256) void k_prep(BatchView bv, int npt) {
             I.P.fill[t] = 0;
         }
         if (ballot(bad) != 0 && lane_id() == 0) atomicOr(&I.P.ctrl->status, ST_BADREF);
+    }
+}
+
+// ------------------------------------------------------- point placement
+//
+// The dominance and the peel work on positions, not on point indices: the
+// points are placed in ascending buckets of their first objective,
+//   bucket(x) = floor((f_1(x) - lo) * PLACE_BUCKETS / (hi - lo)), clamped,
+// (lo, hi: least and largest f_1), a monotone function of f_1 in float32.
+// A point in a lower bucket has a strictly smaller f_1, so it cannot be
+// dominated by a point of a higher bucket. For a tile whose column block
+// lies wholly in lower buckets than its row block ("ordered") one direction
+// of the relation is known to be empty and the other needs no compare of f_1.
+// Within a bucket the positions follow the order of arrival; ranks do not
+// depend on positions, only the internal matrix does.
+
+__device__ __forceinline__ int place_bucket(float x, float lo, float scale) {
+    const float t = (x - lo) * scale;
+    return t >= (float)PLACE_BUCKETS ? PLACE_BUCKETS - 1 : (t > 0.0f ? (int)t : 0);
+}
+
+// bucket range of one instance (scale 0: every point in bucket 0)
+__device__ __forceinline__ void place_range(const Ctrl *ctrl, float &lo, float &scale) {
+    lo = ord2f(ctrl->f1_lo);
+    const float span = ord2f(ctrl->f1_hi) - lo;
+    scale = span > 0.0f && span < INFINITY ? (float)PLACE_BUCKETS / span : 0.0f;
+}
+
+// Per block of 256 points: bucket counts in LDS (a point's rank within its
+// bucket and block from the LDS atomic), then one global atomic per nonempty
+// bucket reserves the block's run of the bucket. Grid: all instances'
+// padded points.
+__global__ __launch_bounds__(256) void k_place_count(BatchView bv) {
+    __shared__ unsigned hist[PLACE_BUCKETS];
+    const Local L = locate(bv.pt_pref, bv.B);
+    CInst &I = bv.tab[L.b];
+    const int j = L.i, M = I.M;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) hist[threadIdx.x + 256 * q] = 0;
+    lds_barrier();
+    int b = 0;
+    unsigned r = 0;
+    if (j < M) {
+        float lo, scale;
+        place_range(I.P.ctrl, lo, scale);
+        b = place_bucket(I.F[(size_t)j * I.m], lo, scale);
+        r = atomicAdd(&hist[b], 1u);
+    }
+    lds_barrier();
+    // the thread's four bins: all four atomics in flight at once
+    static_assert(PLACE_BUCKETS == 4 * 256, "four bins per thread");
+    unsigned cq[4], base[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) cq[q] = hist[threadIdx.x + 256 * q];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+        base[q] = cq[q] ? atomicAdd(&I.P.bcount[threadIdx.x + 256 * q], cq[q]) : 0u;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) hist[threadIdx.x + 256 * q] = base[q];
+    lds_barrier();
+    if (j < M) I.P.pkey[j] = ((unsigned)b << PLACE_RANK_BITS) | (hist[b] + r);
+}
+
+// Every block scans the instance's bucket counts into bucket starts, then
+// each point goes to its position: the objective copy (blocks of 64
+// positions, objective-major within a block), the position's point, and the
+// tile bounds of the position's block (from its first and its last point).
+__global__ __launch_bounds__(256) void k_place_scatter(BatchView bv) {
+    __shared__ int start[PLACE_BUCKETS + 1];
+    __shared__ int wsum[4];
+    const Local L = locate(bv.pt_pref, bv.B);
+    CInst &I = bv.tab[L.b];
+    const int j = L.i, M = I.M, m = I.m;
+    const int t = threadIdx.x, wv = t >> 6;
+    int c[4], sum = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        c[q] = (int)I.P.bcount[4 * t + q];
+        sum += c[q];
+    }
+    const int incl = wave_incl_scan(sum);
+    if (lane_id() == 63) wsum[wv] = incl;
+    lds_barrier();
+    int run = incl - sum;
+    for (int v = 0; v < wv; ++v) run += wsum[v];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        start[4 * t + q] = run;
+        run += c[q];
+    }
+    if (t == 255) start[PLACE_BUCKETS] = run;
+    lds_barrier();
+    if (j < M) {
+        const unsigned key = I.P.pkey[j];
+        const int b = (int)(key >> PLACE_RANK_BITS);
+        const int pos = start[b] + (int)(key & ((1u << PLACE_RANK_BITS) - 1u));
+        I.P.perm[pos] = j;
+        float *dst = I.P.ft + (size_t)(pos >> 6) * m * 64 + (pos & 63);
+        for (int k = 0; k < m; ++k) dst[k * 64] = I.F[(size_t)j * m + k];
+        // tiles (ib, jb) with every point of ib in a lower bucket than the
+        // first point of jb: ib below the block of that bucket's start
+        if ((pos & 63) == 0) I.P.row_ord[pos >> 6] = start[b] >> 6;
+        // words of column block c from row blocks that start after the
+        // bucket of c's last point are zero
+        if ((pos & 63) == 63 || pos == M - 1) I.P.col_end[pos >> 6] = (start[b + 1] + 63) >> 6;
     }
 }
 
@@ -206,6 +337,48 @@ __device__ __forceinline__ void dom_tile(std::integer_sequence<int, Gs...>,
      ...);
 }
 
+// Ordered tiles: every column point i is in a lower placement bucket than
+// every row point j, so f_1(i) < f_1(j): j cannot dominate i, and
+//   i dominates j  <=>  f_i <= f_j in objectives 2 .. m
+// (m - 1 compares per column point, no reverse word).
+template <int MO, int GW, int R>
+__device__ __forceinline__ void dom_step_ord(const ColV<GW> (&v)[MO], const float (&fj)[MO],
+                                             unsigned &a_lo, unsigned &a_hi) {
+    u64 le = ~0ull;
+#pragma unroll
+    for (int k = 1; k < MO; ++k) le &= ballot(v[k].a[R % GW] <= fj[k]);
+    if (R >= 32) a_hi = shift_in(a_hi, le);
+    else a_lo = shift_in(a_lo, le);
+    // keep the step's masks short-lived: unconstrained, the scheduler lifts
+    // every compare of the unrolled tile ahead of the shift chain and runs
+    // out of scalar registers
+    __builtin_amdgcn_sched_barrier(0);
+}
+
+template <int MO, int GW, int g, int... Is>
+__device__ __forceinline__ void dom_group_ord(std::integer_sequence<int, Is...>,
+                                              const NSGA3_RO float *fi, const float (&fj)[MO],
+                                              unsigned &a_lo, unsigned &a_hi) {
+    ColV<GW> v[MO];
+#pragma unroll
+    for (int k = 1; k < MO; ++k) {
+        const NSGA3_RO ColV<GW> &src = *(const NSGA3_RO ColV<GW> *)(fi + k * 64 + GW * g);
+#pragma unroll
+        for (int q = 0; q < GW; ++q) v[k].a[q] = src.a[q];
+    }
+    (dom_step_ord<MO, GW, GW * g + GW - 1 - Is>(v, fj, a_lo, a_hi), ...);
+}
+
+template <int MO, int GW, int... Gs>
+__device__ __forceinline__ void dom_tile_ord(std::integer_sequence<int, Gs...>,
+                                             const NSGA3_RO float *fi, const float (&fj)[MO],
+                                             unsigned &a_lo, unsigned &a_hi) {
+    constexpr int NG = 64 / GW;
+    (dom_group_ord<MO, GW, NG - 1 - Gs>(std::make_integer_sequence<int, GW>{}, fi, fj, a_lo,
+                                        a_hi),
+     ...);
+}
+
 // One wave per work item of the instances with m = MO (the group order[gs ..
 // gs + gn)). The item is a run of G consecutive tiles of its instance's
 // triangle in row-major order (row jb: column blocks ib = 0 .. jb), so every
@@ -230,6 +403,7 @@ __global__ __launch_bounds__(256) void k_dominance(BatchView bv, int gs, int gn,
     const NSGA3_RO float *ft = (const NSGA3_RO float *)I.P.ft;
     u64 *__restrict__ mask = I.P.mask;
     int *__restrict__ nd = I.P.nd;
+    const NSGA3_RO int *row_ord = (const NSGA3_RO int *)I.P.row_ord;
     long long t = item * G;
     const long long t_end = t + G < T ? t + G : T;
     int jb = uniform(row_of(t));
@@ -240,9 +414,19 @@ __global__ __launch_bounds__(256) void k_dominance(BatchView bv, int gs, int gn,
         float fj[MO];
 #pragma unroll
         for (int k = 0; k < MO; ++k) fj[k] = ft[((size_t)jb * MO + k) * 64 + lane];
-        // tiles of this row within the item
+        // tiles of this row within the item: the ordered ones first (they
+        // write only the row's words), then the rest of the row
         const int ib1 = (int)(t_end - t < (long long)(jb + 1 - ib) ? ib + (t_end - t) : jb + 1);
+        const int io = min(ib1, max(ib, uniform(row_ord[jb])));
         int cnt_j = 0;
+        for (; ib < io; ++ib) {
+            unsigned a_lo = 0, a_hi = 0;
+            const NSGA3_RO float *fi = ft + (size_t)ib * MO * 64;
+            dom_tile_ord<MO, GW>(std::make_integer_sequence<int, 64 / GW>{}, fi, fj, a_lo, a_hi);
+            const u64 A = ((u64)a_hi << 32) | a_lo;
+            mask[(size_t)ib * Mp + jglob] = A;
+            cnt_j += __popcll(A);
+        }
         for (; ib < ib1; ++ib) {
             unsigned a_lo = 0, a_hi = 0, b_lo = 0, b_hi = 0;
             const NSGA3_RO float *fi = ft + (size_t)ib * MO * 64;
@@ -429,7 +613,7 @@ struct PeelShared {
     int cleft[PEEL_CACHE_SLOTS][64];  // counts of the cached chunks
     int red_bad[PEEL_WAVES];    // per-wave poll results
     int red_cnt[PEEL_WAVES];
-    u64 val;
+    u64 val, val2;
 };
 
 // Members of front kf in block w, from the tagged words (current tags
@@ -494,12 +678,12 @@ template <int Q>
 __device__ __forceinline__ void load_column(const CInst &I, int c, u64 (&col)[Q]) {
     const int wv = uniform((int)(threadIdx.x >> 6));
     const u64 *p = I.P.mask + (size_t)c * 64 + lane_id();
-    const int W = I.W;
+    const int we = uniform(I.P.col_end[c]);  // zero (and unwritten) from here on
     const size_t Mp = (size_t)I.Mp;
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
         const int w = wv + q * PEEL_WAVES;
-        col[q] = w < W ? p[(size_t)w * Mp] : 0ull;
+        col[q] = w < we ? p[(size_t)w * Mp] : 0ull;
     }
 }
 
@@ -514,7 +698,7 @@ __device__ __forceinline__ void publish(CInst &I, int k, int c, int own, u64 aw,
         store_relaxed(&front_slot(I.P.ring, I.W, k)[2 * c + lane], tag | half);
     }
     if (lane == 0) sh.own_alive[own] = aw & ~newly;
-    if ((newly >> lane) & 1ull) I.rank[c * 64 + lane] = k;  // read only by later kernels
+    if ((newly >> lane) & 1ull) I.rank[I.P.perm[c * 64 + lane]] = k;  // read only by later kernels
 }
 
 // Ranks the points of owned chunk `own` (chunk c of I) that are alive at
@@ -556,12 +740,13 @@ __device__ void peel_chunk_impl(CInst &I, int k, int c, int own, PeelShared &sh,
                 const u64 *__restrict__ src = I.P.mask + (size_t)c * 64 + lane;
                 const u64 *slot = front_slot(I.P.ring, W, k - 1);
                 const size_t Mp = (size_t)I.Mp;
-                for (int w0 = wv; w0 < W; w0 += PEEL_WAVES * BATCH) {
+                const int we = uniform(I.P.col_end[c]);  // zero words from here on
+                for (int w0 = wv; w0 < we; w0 += PEEL_WAVES * BATCH) {
                     u64 x[BATCH], d[BATCH];
 #pragma unroll
                     for (int q = 0; q < BATCH; ++q) {
                         const int w = w0 + q * PEEL_WAVES;
-                        d[q] = w < W ? (STAGED ? sh.dead[w] : tagged_members(slot, w)) : 0ull;
+                        d[q] = w < we ? (STAGED ? sh.dead[w] : tagged_members(slot, w)) : 0ull;
                         x[q] = d[q] ? src[(size_t)w * Mp] : 0ull;
                     }
 #pragma unroll
@@ -625,16 +810,16 @@ __device__ void peel_pair(CInst &I, int k, int c0, int c1, PeelShared &sh, const
 __device__ void count_streamed(CInst &I, int c, PeelShared &sh) {
     const int lane = lane_id();
     const int wv = uniform((int)(threadIdx.x >> 6));
-    const int W = I.W;
+    const int we = uniform(I.P.col_end[c]);  // zero (and unwritten) words from here on
     const size_t Mp = (size_t)I.Mp;
     const u64 *__restrict__ src = I.P.mask + (size_t)c * 64 + lane;
     int acc = 0;
-    for (int w0 = wv; w0 < W; w0 += PEEL_WAVES * 4) {
+    for (int w0 = wv; w0 < we; w0 += PEEL_WAVES * 4) {
         u64 x[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int w = w0 + q * PEEL_WAVES;
-            x[q] = w < W ? src[(size_t)w * Mp] : 0ull;
+            x[q] = w < we ? src[(size_t)w * Mp] : 0ull;
         }
 #pragma unroll
         for (int q = 0; q < 4; ++q) acc += __popcll(x[q]);
@@ -660,59 +845,74 @@ __device__ __forceinline__ void peel_chunk(CInst &I, int k, int c, int own, Peel
 
 // Q > 0: the first PEEL_CACHE_SLOTS chunks a workgroup owns keep their
 // columns in registers (every instance has W <= Q * PEEL_WAVES); further
-// chunks, if any, are streamed.
+// chunks, if any, are streamed. The launch peels chunks c0 .. c0 + nchunk - 1
+// of the batch's chunk order (whole m-groups) and claims them from word tw
+// of each ticket shard.
 template <int Q>
-__global__ __launch_bounds__(64 * PEEL_WAVES) void k_peel(BatchView bv, int nchunk) {
+__global__ __launch_bounds__(64 * PEEL_WAVES) void k_peel(BatchView bv, int c0, int nchunk,
+                                                         int tw) {
     constexpr int BATCH = Q > 0 ? 4 : PEEL_BATCH;  // streamed chunks: fewer registers next to a cache
     __shared__ PeelShared sh;
     const int lane = lane_id();
     const int wv = uniform((int)(threadIdx.x >> 6));
-    const u64 one = lane == 0 ? 1ull : 0ull;
 
     // Front 0: claim chunks until all are claimed. Ticket shard s hands out
     // chunks s, s + TICKET_SHARDS, ...; a workgroup starts at its own shard
     // and moves on when one runs dry (the shards spread the claims over many
-    // addresses). Returns the claimed chunk (uniform), or nchunk or more
-    // when none is left.
+    // addresses). One atomic claims up to `take` (1 or 2) chunks: tickets n
+    // and n + 1 of a shard. Returns the first claimed chunk (uniform; nchunk
+    // or more when none is left) and the second in t2 (nchunk or more when
+    // there is none).
     int nown = 0;
     const int home = (int)(blockIdx.x % TICKET_SHARDS);
     bool home_dry = false;
-    auto claim = [&]() -> u64 {
+    auto claim = [&](int take, u64 &t2) -> u64 {
         if (wv == 0) {
-            u64 t = ~0ull;
+            const u64 add = lane == 0 ? (u64)take : 0ull;
+            u64 t = ~0ull, u = ~0ull;
             for (;;) {
-                if (!home_dry) {
-                    const u64 n = uniform(atomicAdd(&bv.ticket[home * TICKET_STRIDE], one));
-                    const u64 g = (u64)home + (u64)TICKET_SHARDS * n;
-                    if (g < (u64)nchunk) { t = g; break; }
-                    home_dry = true;
+                int s = home;
+                if (home_dry) {
+                    // look at every shard at once; claim from one that has
+                    // chunks left (starting after the home shard), or stop
+                    // when none has
+                    const u64 n_l = lane < TICKET_SHARDS
+                                        ? load_relaxed(&bv.ticket[lane * TICKET_STRIDE + tw])
+                                        : 0ull;
+                    const u64 avail = ballot(lane < TICKET_SHARDS &&
+                                             (u64)lane + (u64)TICKET_SHARDS * n_l < (u64)nchunk);
+                    if (avail == 0) break;
+                    // the 32 shard bits rotated so that the home shard is bit 0
+                    const unsigned a32 = (unsigned)avail;
+                    const unsigned rot = home == 0 ? a32 : ((a32 >> home) | (a32 << (32 - home)));
+                    s = (home + __ffs((int)rot) - 1) % TICKET_SHARDS;
                 }
-                // look at every shard at once; claim from one that has chunks
-                // left (starting after the home shard), or stop when none has
-                const u64 n_l = lane < TICKET_SHARDS ? load_relaxed(&bv.ticket[lane * TICKET_STRIDE]) : 0ull;
-                const u64 avail = ballot(lane < TICKET_SHARDS &&
-                                         (u64)lane + (u64)TICKET_SHARDS * n_l < (u64)nchunk);
-                if (avail == 0) break;
-                // the 32 shard bits rotated so that the home shard is bit 0
-                const unsigned a32 = (unsigned)avail;
-                const unsigned rot = home == 0 ? a32 : ((a32 >> home) | (a32 << (32 - home)));
-                const int s = (home + __ffs((int)rot) - 1) % TICKET_SHARDS;
-                const u64 n = uniform(atomicAdd(&bv.ticket[s * TICKET_STRIDE], one));
+                const u64 n = uniform(atomicAdd(&bv.ticket[s * TICKET_STRIDE + tw], add));
                 const u64 g = (u64)s + (u64)TICKET_SHARDS * n;
-                if (g < (u64)nchunk) { t = g; break; }
+                // the shard's next ticket after these is past the end: dry
+                if (s == home && g + (u64)TICKET_SHARDS * (u64)take >= (u64)nchunk) home_dry = true;
+                if (g < (u64)nchunk) {
+                    t = g;
+                    if (take > 1 && g + TICKET_SHARDS < (u64)nchunk) u = g + TICKET_SHARDS;
+                    break;
+                }
             }
             sh.val = t;
+            sh.val2 = u;
         }
         lds_barrier();
         const u64 t = uniform(sh.val);
+        t2 = uniform(sh.val2);
         lds_barrier();
         return t;
     };
     // Records claimed chunk t as owned chunk nown (wave 0 writes, the
     // caller's next barrier publishes it).
     auto own = [&](u64 t, int &b, int &c) {
-        b = uniform(find_range(bv.chunk_pref, bv.B, (int)t));
-        c = (int)t - bv.chunk_pref[b];
+        const int tt = c0 + (int)t;
+        const int pos = uniform(find_range(bv.chunk_pref, bv.B, tt));
+        b = uniform(bv.order[pos]);
+        c = tt - bv.chunk_pref[pos];
         if (wv == 0) {
             sh.own_b[nown] = b;
             sh.own_c[nown] = c;
@@ -726,13 +926,18 @@ __global__ __launch_bounds__(64 * PEEL_WAVES) void k_peel(BatchView bv, int nchu
     // counting over their column first. Every running workgroup claims until
     // none is left, so every chunk has a running owner.
     bool dry = false;
-    while (nown < (Q > 0 ? PEEL_CACHE_SLOTS : PEEL_OWN_CAP)) {
-        const u64 t = claim();
+    constexpr int FIRST_CAP = Q > 0 ? PEEL_CACHE_SLOTS : PEEL_OWN_CAP;
+    while (nown < FIRST_CAP) {
+        u64 t2;
+        const u64 t = claim(FIRST_CAP - nown >= 2 ? 2 : 1, t2);
         if (t >= (u64)nchunk) { dry = true; break; }
-        int b, c;
-        own(t, b, c);
-        if (Q == 0) peel_chunk<BATCH>(bv.tab[b], 0, c, nown, sh);
-        ++nown;
+        for (u64 tc : {t, t2}) {
+            if (tc >= (u64)nchunk) break;
+            int b, c;
+            own(tc, b, c);
+            if (Q == 0) peel_chunk<BATCH>(bv.tab[b], 0, c, nown, sh);
+            ++nown;
+        }
     }
     lds_barrier();
     u64 col0[Q > 0 ? Q : 1], col1[Q > 0 ? Q : 1];
@@ -767,13 +972,17 @@ __global__ __launch_bounds__(64 * PEEL_WAVES) void k_peel(BatchView bv, int nchu
             lds_barrier();  // the shared partial sums are free again
         }
         while (!dry && nown < PEEL_OWN_CAP) {
-            const u64 t = claim();
+            u64 t2;
+            const u64 t = claim(PEEL_OWN_CAP - nown >= 2 ? 2 : 1, t2);
             if (t >= (u64)nchunk) break;
-            int b, c;
-            own(t, b, c);
-            count_streamed(bv.tab[b], c, sh);
-            peel_chunk<BATCH>(bv.tab[b], 0, c, nown, sh);
-            ++nown;
+            for (u64 tc : {t, t2}) {
+                if (tc >= (u64)nchunk) break;
+                int b, c;
+                own(tc, b, c);
+                count_streamed(bv.tab[b], c, sh);
+                peel_chunk<BATCH>(bv.tab[b], 0, c, nown, sh);
+                ++nown;
+            }
         }
         lds_barrier();
     }
@@ -840,57 +1049,151 @@ __global__ __launch_bounds__(64 * PEEL_WAVES) void k_peel(BatchView bv, int nchu
 hipError_t launch_prepare(const HostPlan &hp, const BatchView &bv, bool init_done, hipStream_t s) {
     if (!init_done) NSGA3_LAUNCH("init", k_init, dim3(hp.B), dim3(256), 0, s, bv);
     NSGA3_LAUNCH("prep", k_prep, dim3((hp.npt + hp.nref) / 256), dim3(256), 0, s, bv, hp.npt);
+    if (bv.run & RUN_ND) {
+        NSGA3_LAUNCH("place_count", k_place_count, dim3(hp.npt / 256), dim3(256), 0, s, bv);
+        NSGA3_LAUNCH("place_scatter", k_place_scatter, dim3(hp.npt / 256), dim3(256), 0, s, bv);
+    }
     return hipGetLastError();
 }
 
-hipError_t launch_nd_sort(const HostPlan &hp, const BatchView &bv, hipStream_t s) {
-    // Columns stay in registers when every instance's column fits a cache
-    // and two cached chunks per compute unit hold all chunks (one workgroup
-    // per compute unit at that register use); otherwise they are streamed.
-    // A peel with cached columns counts dominators from them; a streamed one
-    // takes the counts fused into the dominance kernel (its front 0 then
-    // needs no pass over the matrix).
-    const int cus = device_info().cus;
-    int q = 0;
-    if (hp.nchunk <= PEEL_CACHE_SLOTS * cus) {
-        for (int c : {16, 24, 32, 40, 48})
-            if (hp.max_W <= c * PEEL_WAVES) {
-                q = c;
-                break;
-            }
+// Column caching of a peel over `nchunk` chunks whose widest instance has
+// W = max_W: columns stay in registers (returns the per-wave cache size) when
+// every column fits a cache and two cached chunks per compute unit hold all
+// chunks (one workgroup per compute unit at that register use); otherwise
+// they are streamed (returns 0). A peel with cached columns counts dominators
+// from them; a streamed one takes the counts fused into the dominance kernel
+// (its front 0 then needs no pass over the matrix).
+static int peel_cache(int nchunk, int max_W, int cus) {
+    if (nchunk > PEEL_CACHE_SLOTS * cus) return 0;
+    for (int c : {16, 24, 32, 40, 48})
+        if (max_W <= c * PEEL_WAVES) return c;
+    return 0;
+}
+
+// Workgroups of a peel: one per compute unit with cached columns (their
+// register use), else `streamed_per_cu` per compute unit.
+static void launch_peel(const BatchView &bv, int q, int c0, int nchunk, int tw, int cus,
+                        int streamed_per_cu, hipStream_t s) {
+    const int cap = q ? cus : streamed_per_cu * cus;
+    const dim3 pg(nchunk < cap ? nchunk : cap), pb(64 * PEEL_WAVES);
+    switch (q) {
+        case 16: NSGA3_LAUNCH("peel", k_peel<16>, pg, pb, 0, s, bv, c0, nchunk, tw); break;
+        case 24: NSGA3_LAUNCH("peel", k_peel<24>, pg, pb, 0, s, bv, c0, nchunk, tw); break;
+        case 32: NSGA3_LAUNCH("peel", k_peel<32>, pg, pb, 0, s, bv, c0, nchunk, tw); break;
+        case 40: NSGA3_LAUNCH("peel", k_peel<40>, pg, pb, 0, s, bv, c0, nchunk, tw); break;
+        case 48: NSGA3_LAUNCH("peel", k_peel<48>, pg, pb, 0, s, bv, c0, nchunk, tw); break;
+        default: NSGA3_LAUNCH("peel", k_peel<0>, pg, pb, 0, s, bv, c0, nchunk, tw); break;
     }
-    for (int g = 0; g < hp.ngroups; ++g) {
-        const int gs = hp.grp_start[g], gn = hp.grp_start[g + 1] - gs;
-        const long long item0 = hp.grp_dom[g], n_items = hp.grp_dom[g + 1] - item0;
-        const unsigned blocks = (unsigned)((n_items + 3) / 4);
+}
+
+static void launch_dominance(const HostPlan &hp, const BatchView &bv, int g, bool counts,
+                             hipStream_t s) {
+    const int gs = hp.grp_start[g], gn = hp.grp_start[g + 1] - gs;
+    const long long item0 = hp.grp_dom[g], n_items = hp.grp_dom[g + 1] - item0;
+    const unsigned blocks = (unsigned)((n_items + 3) / 4);
+    const int cf = counts ? 1 : 0;
 #define NSGA3_DOM_CASE(MO)                                                                       \
     case MO:                                                                                     \
         NSGA3_LAUNCH("dominance", k_dominance<MO>, dim3(blocks), dim3(256), 0, s, bv, gs, gn,   \
-                     item0, n_items, q == 0 ? 1 : 0);                                            \
+                     item0, n_items, cf);                                                        \
         break;
-        switch (hp.grp_m[g]) {
-            NSGA3_DOM_CASE(2) NSGA3_DOM_CASE(3) NSGA3_DOM_CASE(4) NSGA3_DOM_CASE(5)
-            NSGA3_DOM_CASE(6) NSGA3_DOM_CASE(7) NSGA3_DOM_CASE(8) NSGA3_DOM_CASE(9)
-            NSGA3_DOM_CASE(10) NSGA3_DOM_CASE(11) NSGA3_DOM_CASE(12) NSGA3_DOM_CASE(13)
-            NSGA3_DOM_CASE(14) NSGA3_DOM_CASE(15) NSGA3_DOM_CASE(16)
-            default:
-                NSGA3_LAUNCH("dominance", k_dominance_wide, dim3(blocks), dim3(256), 0, s, bv, gs,
-                             gn, item0, n_items, q == 0 ? 1 : 0);
-                break;
-        }
+    switch (hp.grp_m[g]) {
+        NSGA3_DOM_CASE(2) NSGA3_DOM_CASE(3) NSGA3_DOM_CASE(4) NSGA3_DOM_CASE(5)
+        NSGA3_DOM_CASE(6) NSGA3_DOM_CASE(7) NSGA3_DOM_CASE(8) NSGA3_DOM_CASE(9)
+        NSGA3_DOM_CASE(10) NSGA3_DOM_CASE(11) NSGA3_DOM_CASE(12) NSGA3_DOM_CASE(13)
+        NSGA3_DOM_CASE(14) NSGA3_DOM_CASE(15) NSGA3_DOM_CASE(16)
+        default:
+            NSGA3_LAUNCH("dominance", k_dominance_wide, dim3(blocks), dim3(256), 0, s, bv, gs, gn,
+                         item0, n_items, cf);
+            break;
+    }
 #undef NSGA3_DOM_CASE
+}
+
+// Pipelined peel of a batch with several m-groups: each group's peel runs on
+// a side stream as soon as that group's dominance launch is done, beside the
+// dominance launches of the later groups (the peel is bound by the latency of
+// its fronts, the dominance by vector issue). The side stream forks from the
+// caller's stream and joins it again through events, so the call stays one
+// ordered piece of work on the caller's stream and can be captured in a
+// graph. One side stream and event set per device, made on the first batched
+// call outside a capture and kept until the process ends; a mutex orders
+// their use by calls from several host threads.
+// Workgroups per compute unit of a streamed peel beside dominance launches
+// (the rest of each compute unit's wave slots stay with the dominance).
+constexpr int PEEL_PIPE_PER_CU = 1;
+
+struct PeelPipe {
+    hipStream_t side = nullptr;
+    hipEvent_t ev[PEEL_PIPE_GROUPS + 1] = {};
+};
+static std::mutex g_pipe_mu;
+static PeelPipe g_pipe[64];
+
+static unsigned long long capture_id(hipStream_t s, bool &capturing, bool &ok) {
+    hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+    unsigned long long id = 0;
+    ok = hipStreamGetCaptureInfo(s, &st, &id) == hipSuccess &&
+         st != hipStreamCaptureStatusInvalidated;
+    capturing = st == hipStreamCaptureStatusActive;
+    return id;
+}
+
+// The device's pipe if the peel may be pipelined now, else null (the caller
+// then peels in one launch): the pipe is made outside a capture only, and its
+// side stream must be idle in capture terms or in the caller's own capture.
+static PeelPipe *pipe_for(hipStream_t s) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+    bool cap_s, ok_s;
+    const unsigned long long id_s = capture_id(s, cap_s, ok_s);
+    if (!ok_s) return nullptr;
+    PeelPipe &p = g_pipe[dev];
+    if (!p.side) {
+        if (cap_s) return nullptr;
+        hipStream_t side;
+        if (hipStreamCreateWithFlags(&side, hipStreamNonBlocking) != hipSuccess) return nullptr;
+        for (int i = 0; i <= PEEL_PIPE_GROUPS; ++i)
+            if (hipEventCreateWithFlags(&p.ev[i], hipEventDisableTiming) != hipSuccess) {
+                for (int k = 0; k < i; ++k) (void)hipEventDestroy(p.ev[k]);
+                (void)hipStreamDestroy(side);
+                return nullptr;
+            }
+        p.side = side;
     }
-    const int cap = q ? cus : 3 * cus;
-    const int peel_blocks = hp.nchunk < cap ? hp.nchunk : cap;
-    const dim3 pg(peel_blocks), pb(64 * PEEL_WAVES);
-    switch (q) {
-        case 16: NSGA3_LAUNCH("peel", k_peel<16>, pg, pb, 0, s, bv, hp.nchunk); break;
-        case 24: NSGA3_LAUNCH("peel", k_peel<24>, pg, pb, 0, s, bv, hp.nchunk); break;
-        case 32: NSGA3_LAUNCH("peel", k_peel<32>, pg, pb, 0, s, bv, hp.nchunk); break;
-        case 40: NSGA3_LAUNCH("peel", k_peel<40>, pg, pb, 0, s, bv, hp.nchunk); break;
-        case 48: NSGA3_LAUNCH("peel", k_peel<48>, pg, pb, 0, s, bv, hp.nchunk); break;
-        default: NSGA3_LAUNCH("peel", k_peel<0>, pg, pb, 0, s, bv, hp.nchunk); break;
+    bool cap_side, ok_side;
+    const unsigned long long id_side = capture_id(p.side, cap_side, ok_side);
+    if (!ok_side || (cap_side && (!cap_s || id_side != id_s))) return nullptr;
+    return &p;
+}
+
+hipError_t launch_nd_sort(const HostPlan &hp, const BatchView &bv, hipStream_t s) {
+    const int cus = device_info().cus;
+    if (hp.B > 1 && hp.ngroups > 1 && hp.ngroups <= PEEL_PIPE_GROUPS) {
+        std::lock_guard<std::mutex> lock(g_pipe_mu);
+        if (PeelPipe *p = pipe_for(s)) {
+            hipError_t e = hipSuccess;
+            for (int g = 0; g < hp.ngroups && e == hipSuccess; ++g) {
+                const int c0 = hp.grp_chunk[g], nc = hp.grp_chunk[g + 1] - c0;
+                const int q = peel_cache(nc, hp.grp_max_W[g], cus);
+                launch_dominance(hp, bv, g, q == 0, s);
+                e = hipEventRecord(p->ev[g], s);
+                if (e == hipSuccess) e = hipStreamWaitEvent(p->side, p->ev[g], 0);
+                if (e == hipSuccess) launch_peel(bv, q, c0, nc, g, cus, PEEL_PIPE_PER_CU, p->side);
+            }
+            // join even after an error, so that the side stream leaves no
+            // open fork in a capture
+            const hipError_t ej = hipEventRecord(p->ev[PEEL_PIPE_GROUPS], p->side);
+            const hipError_t ew = ej == hipSuccess
+                                      ? hipStreamWaitEvent(s, p->ev[PEEL_PIPE_GROUPS], 0)
+                                      : ej;
+            if (e == hipSuccess) e = ew;
+            return e == hipSuccess ? hipGetLastError() : e;
+        }
     }
+    const int q = peel_cache(hp.nchunk, hp.max_W, cus);
+    for (int g = 0; g < hp.ngroups; ++g) launch_dominance(hp, bv, g, q == 0, s);
+    launch_peel(bv, q, 0, hp.nchunk, 0, cus, 3, s);
     return hipGetLastError();
 }
 

@@ -62,6 +62,7 @@ struct Ctrl {
     int ext_out[NSGA3_MAX_OBJECTIVES];
     int degen_out;
     int ext_done;            // blocks of the extreme search that finished
+    unsigned f1_lo, f1_hi;   // least and largest first objective, order-preserving encoding
 };
 
 // front ring of the peel: PEEL_RING slots, each with two tagged words per
@@ -72,12 +73,18 @@ constexpr int PT_ALIGN = 256;    // per-instance point and reference ranges are 
 constexpr int COMPACT_TILE = 256;  // points per compaction tile (one workgroup)
 constexpr int TICKET_SHARDS = 32;   // peel chunk-claim counters of a batch
 constexpr int TICKET_STRIDE = 32;   // u64 words between them (256 bytes)
+constexpr int PLACE_BUCKETS = 1024;  // first-objective buckets of the point placement
+constexpr int PLACE_RANK_BITS = 20;  // place key: bucket << PLACE_RANK_BITS | rank in bucket
+static_assert(NSGA3_MAX_POINTS <= (1 << PLACE_RANK_BITS), "ranks in a bucket fit the key");
+constexpr int PEEL_PIPE_GROUPS = 8; // most m-groups whose peels run one per group
+                                    // (word g of each shard counts group g)
 
 // Byte offsets of one instance's workspace regions (all 256-byte aligned).
 struct Layout {
     int M, m, H, N, Mp, W, Hp;
-    size_t ctrl, ft, nd, mask, ring, list, fn, rank, pi, dist, akey, wn,
-        rho, cnt, off, fill, tpick, members, qrow, picked, tcnt, remain, emat, total;
+    size_t ctrl, ft, nd, mask, ring, perm, pkey, bcount, row_ord, col_end, list, fn, rank, pi,
+        dist, akey, wn, rho, cnt, off, fill, tpick, members, qrow, picked, tcnt, remain, emat,
+        total;
 };
 
 Layout make_layout(int M, int m, int H, int N);
@@ -88,6 +95,12 @@ struct Ptrs {
     int *nd;
     u64 *mask;
     u64 *ring;          // peel front ring (tagged members per front)
+    // Point placement (dominance and peel work on positions, not indices):
+    int *perm;          // point at each position
+    unsigned *pkey;     // per point: bucket << PLACE_RANK_BITS | rank within the bucket
+    unsigned *bcount;   // points per bucket (PLACE_BUCKETS)
+    int *row_ord;       // per row block jb: tiles (ib, jb) with ib < row_ord[jb] are ordered
+    int *col_end;       // per column block c: its words from row block col_end[c] on are zero
     int *list;
     float *fn;
     int *rank, *pi;
@@ -135,7 +148,8 @@ typedef const NSGA3_RO Inst CInst;
 // Global index ranges: instance b owns [pref[b], pref[b+1]) of each kind.
 // Point and reference ranges are padded to PT_ALIGN so that no 256-thread
 // block straddles two instances. dom_pref / asc_pref run over `order`
-// (instances sorted by m) and count per-wave work items.
+// (instances sorted by m) and count per-wave work items; chunk_pref runs
+// over `order` too, so that the chunks of one m-group are contiguous.
 struct BatchView {
     CInst *tab;
     const NSGA3_RO int *pt_pref;
@@ -144,7 +158,7 @@ struct BatchView {
     const NSGA3_RO int *order;
     const NSGA3_RO long long *dom_pref;
     const NSGA3_RO long long *asc_pref;
-    u64 *ticket;        // batch-level peel chunk-claim counters (TICKET_SHARDS)
+    u64 *ticket;        // peel chunk-claim counters (TICKET_SHARDS x TICKET_STRIDE words)
     int B;
     int run;            // RUN_* flags of this call
 };
@@ -354,6 +368,8 @@ __device__ __forceinline__ void init_instance(Ctrl *ctrl, int *front_info, int n
         ctrl->list_count = 0;
         ctrl->ext_done = 0;
         if (run & RUN_ND) {
+            ctrl->f1_lo = 0xffffffffu;
+            ctrl->f1_hi = 0u;
             // a defined value even if the peel stops on an internal error
             front_info[0] = 0;
             front_info[1] = 0;
@@ -384,6 +400,8 @@ struct HostPlan {
     int grp_start[NSGA3_MAX_OBJECTIVES + 2];       // range of `order` per group
     long long grp_dom[NSGA3_MAX_OBJECTIVES + 2];   // dominance items before each group
     long long grp_asc[NSGA3_MAX_OBJECTIVES + 2];   // association items before each group
+    int grp_chunk[NSGA3_MAX_OBJECTIVES + 2];       // 64-point chunks before each group
+    int grp_max_W[NSGA3_MAX_OBJECTIVES + 1];       // widest instance of each group
     int max_W;
 };
 
