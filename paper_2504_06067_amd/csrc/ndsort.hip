@@ -355,18 +355,34 @@ __device__ __forceinline__ void dom_step_ord(const ColV<GW> (&v)[MO], const floa
     __builtin_amdgcn_sched_barrier(0);
 }
 
-template <int MO, int GW, int g, int... Is>
-__device__ __forceinline__ void dom_group_ord(std::integer_sequence<int, Is...>,
-                                              const NSGA3_RO float *fi, const float (&fj)[MO],
-                                              unsigned &a_lo, unsigned &a_hi) {
-    ColV<GW> v[MO];
+// Column values of group g (points GW*g .. GW*g + GW - 1) for objectives
+// 2 .. m: one scalar load per objective.
+template <int MO, int GW, int g>
+__device__ __forceinline__ void load_group_ord(const NSGA3_RO float *fi, ColV<GW> (&v)[MO]) {
 #pragma unroll
     for (int k = 1; k < MO; ++k) {
         const NSGA3_RO ColV<GW> &src = *(const NSGA3_RO ColV<GW> *)(fi + k * 64 + GW * g);
 #pragma unroll
         for (int q = 0; q < GW; ++q) v[k].a[q] = src.a[q];
     }
-    (dom_step_ord<MO, GW, GW * g + GW - 1 - Is>(v, fj, a_lo, a_hi), ...);
+}
+
+// Group g of an ordered tile, column points GW*g + GW - 1 down to GW*g, from
+// `cur`, while the loads of group g - 1 fill `nxt`. Scalar loads return in
+// any order, so a wait for `cur` would also wait for loads issued after it:
+// the group waits first, then issues the next group's loads, then computes.
+template <int MO, int GW, int g, int... Is>
+__device__ __forceinline__ void dom_group_ord(std::integer_sequence<int, Is...>,
+                                              const NSGA3_RO float *fi, const float (&fj)[MO],
+                                              ColV<GW> (&cur)[MO], ColV<GW> (&nxt)[MO],
+                                              unsigned &a_lo, unsigned &a_hi) {
+    __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0)
+    __builtin_amdgcn_sched_barrier(0);
+    if constexpr (g > 0) load_group_ord<MO, GW, g - 1>(fi, nxt);
+    __builtin_amdgcn_sched_barrier(0);
+    (dom_step_ord<MO, GW, GW * g + GW - 1 - Is>(cur, fj, a_lo, a_hi), ...);
+#pragma unroll
+    for (int k = 1; k < MO; ++k) cur[k] = nxt[k];
 }
 
 template <int MO, int GW, int... Gs>
@@ -374,8 +390,10 @@ __device__ __forceinline__ void dom_tile_ord(std::integer_sequence<int, Gs...>,
                                              const NSGA3_RO float *fi, const float (&fj)[MO],
                                              unsigned &a_lo, unsigned &a_hi) {
     constexpr int NG = 64 / GW;
-    (dom_group_ord<MO, GW, NG - 1 - Gs>(std::make_integer_sequence<int, GW>{}, fi, fj, a_lo,
-                                        a_hi),
+    ColV<GW> cur[MO], nxt[MO];
+    load_group_ord<MO, GW, NG - 1>(fi, cur);
+    (dom_group_ord<MO, GW, NG - 1 - Gs>(std::make_integer_sequence<int, GW>{}, fi, fj, cur, nxt,
+                                        a_lo, a_hi),
      ...);
 }
 
