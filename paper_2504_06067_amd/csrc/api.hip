@@ -189,9 +189,9 @@ __global__ __launch_bounds__(256) void k_blob(Blob b, unsigned *dst, int n) {
 // (as k_init), in one launch.
 __global__ __launch_bounds__(256) void k_blob_init(Blob b, unsigned *dst, int n, Ctrl *ctrl,
                                                    int *front_info, int n_stop, int run,
-                                                   u64 *ticket) {
+                                                   unsigned *bcount, u64 *ticket) {
     for (int i = threadIdx.x; i < n; i += 256) dst[i] = b.w[i];
-    init_instance(ctrl, front_info, n_stop, run, threadIdx.x);
+    init_instance(ctrl, front_info, n_stop, run, bcount, threadIdx.x);
     if (threadIdx.x < TICKET_SHARDS) ticket[threadIdx.x * TICKET_STRIDE] = 0;
 }
 
@@ -353,7 +353,7 @@ static hipError_t enqueue(Plan &p, char *ws, hipStream_t s) {
         memcpy(&I0, p.hdr.data() + p.hl.tab, sizeof(Inst));
         NSGA3_LAUNCH("header", k_blob_init, dim3(1), dim3(256), 0, s, blob,
                      (unsigned *)(ws + p.inst_total), (int)(p.hdr.size() / 4), I0.P.ctrl,
-                     I0.front_info, I0.n_stop, p.bv.run, p.bv.ticket);
+                     I0.front_info, I0.n_stop, p.bv.run, I0.P.bcount, p.bv.ticket);
         e = hipGetLastError();
     } else {
         e = upload(p.hdr.data(), p.hdr.size(), ws + p.inst_total, s);

@@ -25,10 +25,30 @@ long long dominance_tiles(int W) { return (long long)W * (W + 1) / 2; }
 
 __global__ __launch_bounds__(256) void k_init(BatchView bv) {
     CInst &I = bv.tab[blockIdx.x];
-    init_instance(I.P.ctrl, I.front_info, I.n_stop, bv.run, threadIdx.x);
+    init_instance(I.P.ctrl, I.front_info, I.n_stop, bv.run, I.P.bcount, threadIdx.x);
     static_assert(TICKET_SHARDS * PEEL_PIPE_GROUPS <= 256, "one word per thread");
     if (blockIdx.x == 0 && threadIdx.x < TICKET_SHARDS * PEEL_PIPE_GROUPS)
         bv.ticket[(threadIdx.x % TICKET_SHARDS) * TICKET_STRIDE + threadIdx.x / TICKET_SHARDS] = 0;
+}
+
+// ------------------------------------------------------- point placement
+//
+// The dominance and the peel work on positions, not on point indices: the
+// points are placed in ascending buckets of their first objective,
+//   bucket(x) = floor((f_1(x) - lo) * PLACE_BUCKETS / (hi - lo)), clamped,
+// (lo, hi: least and largest f_1 of a strided sample of 256 points), a
+// monotone function of f_1 in float32. k_prep counts the buckets, and
+// k_place_scatter places the points.
+// A point in a lower bucket has a strictly smaller f_1, so it cannot be
+// dominated by a point of a higher bucket. For a tile whose column block
+// lies wholly in lower buckets than its row block ("ordered") one direction
+// of the relation is known to be empty and the other needs no compare of f_1.
+// Within a bucket the positions follow the order of arrival; ranks do not
+// depend on positions, only the internal matrix does.
+
+__device__ __forceinline__ int place_bucket(float x, float lo, float scale) {
+    const float t = (x - lo) * scale;
+    return t >= (float)PLACE_BUCKETS ? PLACE_BUCKETS - 1 : (t > 0.0f ? (int)t : 0);
 }
 
 // Grid: [all instances' padded points][all instances' padded references].
@@ -46,13 +66,12 @@ __global__ __launch_bounds__(256) void k_prep(BatchView bv, int npt) {
         // same float. Reduced per wave, then per block in LDS: one atomic
         // per block and objective (atomics on one address serialize).
         const bool ideal_here = (bv.run & RUN_ND) && (bv.run & RUN_NORM) && m <= NARROW_M;
-        // objective k of the wave's points reduced to its least value (the
-        // ideal point) and, for k = 0, also to its largest (the range of the
-        // placement buckets); slot NARROW_M holds the largest first objective
-        __shared__ unsigned s_lo[4][NARROW_M + 1];
+        __shared__ unsigned s_lo[4][NARROW_M];
+        __shared__ unsigned s_rng[2][4];
+        __shared__ unsigned hist[PLACE_BUCKETS];
         const int wv = threadIdx.x >> 6;
-        if ((bv.run & RUN_ND) && lane_id() <= NARROW_M)
-            s_lo[wv][lane_id()] = lane_id() == NARROW_M ? 0u : 0xffffffffu;
+        if (ideal_here && lane_id() < m) s_lo[wv][lane_id()] = 0xffffffffu;
+        float f1 = 0.0f;  // this point's first objective
         if (j < Mp && (bv.run & RUN_ND)) {
             for (int k = 0; k < m; ++k) {
                 float v = INFINITY;
@@ -63,13 +82,10 @@ __global__ __launch_bounds__(256) void k_prep(BatchView bv, int npt) {
                     // padding positions (the placement fills positions < M)
                     I.P.ft[((size_t)(j >> 6) * m + k) * 64 + (j & 63)] = v;
                 }
-                if (ideal_here || k == 0) {
+                if (k == 0) f1 = v;
+                if (ideal_here) {
                     const unsigned lo = wave_min_u32(j < M ? f2ord(v) : 0xffffffffu);
                     if (lane_id() == 0) s_lo[wv][k] = lo;
-                }
-                if (k == 0) {
-                    const unsigned hi = wave_max_u32(j < M ? f2ord(v) : 0u);
-                    if (lane_id() == 0) s_lo[wv][NARROW_M] = hi;
                 }
             }
             I.P.nd[j] = 0;
@@ -85,27 +101,51 @@ __global__ __launch_bounds__(256) void k_prep(BatchView bv, int npt) {
                 }
             }
         }
-        // every instance's point range starts with a whole block (PT_ALIGN)
-        static_assert(PLACE_BUCKETS <= 4 * PT_ALIGN, "four bucket counts per thread");
-        if ((bv.run & RUN_ND) && j < PLACE_BUCKETS / 4) {
-#pragma unroll
-            for (int q = 0; q < 4; ++q) I.P.bcount[4 * j + q] = 0;
-        }
         if (bv.run & RUN_ND) {
-            // the run flags and the points branch are uniform over the block
-            lds_barrier();
-            const int k = threadIdx.x;
-            if (k < (ideal_here ? m : 1)) {
-                const unsigned lo = min(min(s_lo[0][k], s_lo[1][k]), min(s_lo[2][k], s_lo[3][k]));
-                if (lo != 0xffffffffu) {
-                    if (ideal_here) atomicMin(&I.P.ctrl->zmin_enc[k], lo);
-                    if (k == 0) atomicMin(&I.P.ctrl->f1_lo, lo);
-                }
-            } else if (k == 64) {
-                const unsigned hi = max(max(s_lo[0][NARROW_M], s_lo[1][NARROW_M]),
-                                        max(s_lo[2][NARROW_M], s_lo[3][NARROW_M]));
-                if (hi != 0u) atomicMax(&I.P.ctrl->f1_hi, hi);
+            // (the run flags and the points branch are uniform over the block)
+            // Placement counts (see k_place_scatter). The bucket range is that
+            // of a strided sample of 256 points, the same in every block, so
+            // no pass over all points precedes the bucketing; points outside
+            // it clamp to the end buckets, which keeps the bucket function
+            // monotone (the range only decides how many tiles are ordered).
+            const int js = (int)(((long long)threadIdx.x * M) >> 8);
+            const unsigned sv = f2ord(I.F[(size_t)js * m]);
+            const unsigned wlo = wave_min_u32(sv), whi = wave_max_u32(sv);
+            if (lane_id() == 0) {
+                s_rng[0][wv] = wlo;
+                s_rng[1][wv] = whi;
             }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) hist[threadIdx.x + 256 * q] = 0;
+            lds_barrier();
+            if (ideal_here && (int)threadIdx.x < m) {
+                const int k = threadIdx.x;
+                const unsigned lo = min(min(s_lo[0][k], s_lo[1][k]), min(s_lo[2][k], s_lo[3][k]));
+                if (lo != 0xffffffffu) atomicMin(&I.P.ctrl->zmin_enc[k], lo);
+            }
+            const float lo = ord2f(min(min(s_rng[0][0], s_rng[0][1]), min(s_rng[0][2], s_rng[0][3])));
+            const float hi = ord2f(max(max(s_rng[1][0], s_rng[1][1]), max(s_rng[1][2], s_rng[1][3])));
+            const float span = hi - lo;
+            const float scale = span > 0.0f && span < INFINITY ? (float)PLACE_BUCKETS / span : 0.0f;
+            int b = 0;
+            unsigned r = 0;
+            if (j < M) {
+                b = place_bucket(f1, lo, scale);
+                r = atomicAdd(&hist[b], 1u);  // rank within the bucket and block
+            }
+            lds_barrier();
+            // the thread's four bins: one global atomic per nonempty bin
+            // reserves the block's run of the bucket (all four in flight)
+            unsigned cq[4], base[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) cq[q] = hist[threadIdx.x + 256 * q];
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                base[q] = cq[q] ? atomicAdd(&I.P.bcount[threadIdx.x + 256 * q], cq[q]) : 0u;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) hist[threadIdx.x + 256 * q] = base[q];
+            lds_barrier();
+            if (j < M) I.P.pkey[j] = ((unsigned)b << PLACE_RANK_BITS) | (hist[b] + r);
         }
         if (j < M && (bv.run & RUN_NICHE)) {
             I.P.picked[j] = 0;
@@ -145,66 +185,6 @@ __global__ __launch_bounds__(256) void k_prep(BatchView bv, int npt) {
         }
         if (ballot(bad) != 0 && lane_id() == 0) atomicOr(&I.P.ctrl->status, ST_BADREF);
     }
-}
-
-// ------------------------------------------------------- point placement
-//
-// The dominance and the peel work on positions, not on point indices: the
-// points are placed in ascending buckets of their first objective,
-//   bucket(x) = floor((f_1(x) - lo) * PLACE_BUCKETS / (hi - lo)), clamped,
-// (lo, hi: least and largest f_1), a monotone function of f_1 in float32.
-// A point in a lower bucket has a strictly smaller f_1, so it cannot be
-// dominated by a point of a higher bucket. For a tile whose column block
-// lies wholly in lower buckets than its row block ("ordered") one direction
-// of the relation is known to be empty and the other needs no compare of f_1.
-// Within a bucket the positions follow the order of arrival; ranks do not
-// depend on positions, only the internal matrix does.
-
-__device__ __forceinline__ int place_bucket(float x, float lo, float scale) {
-    const float t = (x - lo) * scale;
-    return t >= (float)PLACE_BUCKETS ? PLACE_BUCKETS - 1 : (t > 0.0f ? (int)t : 0);
-}
-
-// bucket range of one instance (scale 0: every point in bucket 0)
-__device__ __forceinline__ void place_range(const Ctrl *ctrl, float &lo, float &scale) {
-    lo = ord2f(ctrl->f1_lo);
-    const float span = ord2f(ctrl->f1_hi) - lo;
-    scale = span > 0.0f && span < INFINITY ? (float)PLACE_BUCKETS / span : 0.0f;
-}
-
-// Per block of 256 points: bucket counts in LDS (a point's rank within its
-// bucket and block from the LDS atomic), then one global atomic per nonempty
-// bucket reserves the block's run of the bucket. Grid: all instances'
-// padded points.
-__global__ __launch_bounds__(256) void k_place_count(BatchView bv) {
-    __shared__ unsigned hist[PLACE_BUCKETS];
-    const Local L = locate(bv.pt_pref, bv.B);
-    CInst &I = bv.tab[L.b];
-    const int j = L.i, M = I.M;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) hist[threadIdx.x + 256 * q] = 0;
-    lds_barrier();
-    int b = 0;
-    unsigned r = 0;
-    if (j < M) {
-        float lo, scale;
-        place_range(I.P.ctrl, lo, scale);
-        b = place_bucket(I.F[(size_t)j * I.m], lo, scale);
-        r = atomicAdd(&hist[b], 1u);
-    }
-    lds_barrier();
-    // the thread's four bins: all four atomics in flight at once
-    static_assert(PLACE_BUCKETS == 4 * 256, "four bins per thread");
-    unsigned cq[4], base[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) cq[q] = hist[threadIdx.x + 256 * q];
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
-        base[q] = cq[q] ? atomicAdd(&I.P.bcount[threadIdx.x + 256 * q], cq[q]) : 0u;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) hist[threadIdx.x + 256 * q] = base[q];
-    lds_barrier();
-    if (j < M) I.P.pkey[j] = ((unsigned)b << PLACE_RANK_BITS) | (hist[b] + r);
 }
 
 // Every block scans the instance's bucket counts into bucket starts, then
@@ -1067,10 +1047,8 @@ __global__ __launch_bounds__(64 * PEEL_WAVES) void k_peel(BatchView bv, int c0, 
 hipError_t launch_prepare(const HostPlan &hp, const BatchView &bv, bool init_done, hipStream_t s) {
     if (!init_done) NSGA3_LAUNCH("init", k_init, dim3(hp.B), dim3(256), 0, s, bv);
     NSGA3_LAUNCH("prep", k_prep, dim3((hp.npt + hp.nref) / 256), dim3(256), 0, s, bv, hp.npt);
-    if (bv.run & RUN_ND) {
-        NSGA3_LAUNCH("place_count", k_place_count, dim3(hp.npt / 256), dim3(256), 0, s, bv);
+    if (bv.run & RUN_ND)
         NSGA3_LAUNCH("place_scatter", k_place_scatter, dim3(hp.npt / 256), dim3(256), 0, s, bv);
-    }
     return hipGetLastError();
 }
 

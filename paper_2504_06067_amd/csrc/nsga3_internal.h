@@ -62,7 +62,6 @@ struct Ctrl {
     int ext_out[NSGA3_MAX_OBJECTIVES];
     int degen_out;
     int ext_done;            // blocks of the extreme search that finished
-    unsigned f1_lo, f1_hi;   // least and largest first objective, order-preserving encoding
 };
 
 // front ring of the peel: PEEL_RING slots, each with two tagged words per
@@ -362,14 +361,12 @@ struct ProfScope {
 // Per-instance start of a call (one workgroup, thread t): status, list
 // counter, front fill default, normalization accumulators.
 __device__ __forceinline__ void init_instance(Ctrl *ctrl, int *front_info, int n_stop, int run,
-                                              int t) {
+                                              unsigned *bcount, int t) {
     if (t == 0) {
         ctrl->status = 0;
         ctrl->list_count = 0;
         ctrl->ext_done = 0;
         if (run & RUN_ND) {
-            ctrl->f1_lo = 0xffffffffu;
-            ctrl->f1_hi = 0u;
             // a defined value even if the peel stops on an internal error
             front_info[0] = 0;
             front_info[1] = 0;
@@ -381,6 +378,11 @@ __device__ __forceinline__ void init_instance(Ctrl *ctrl, int *front_info, int n
         ctrl->zmin_enc[k] = 0xffffffffu;
         ctrl->fmax_enc[k] = 0u;
         ctrl->ext_key[k] = ~0ull;
+    }
+    if (run & RUN_ND) {
+        static_assert(PLACE_BUCKETS == 4 * 256, "four bucket counts per thread");
+#pragma unroll
+        for (int q = 0; q < 4; ++q) bcount[t + 256 * q] = 0;  // placement counts
     }
 }
 
