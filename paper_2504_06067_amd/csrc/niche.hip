@@ -76,6 +76,10 @@ __device__ __forceinline__ long long block_sum_ll(long long v, long long *red) {
 constexpr int PLAN_PER = 12;
 constexpr int PLAN_WAVES = PLAN_THREADS / 64;
 constexpr int PLAN_TCAP = 2048;  // members of T whose keys are gathered in LDS
+// Largest |T| whose threshold key is found by counting ranks (|T|^2
+// compares, from LDS); larger ones take the radix passes, whose cost is a
+// few block barriers whatever |T|.
+constexpr int PLAN_COUNT_MAX = 256;
 
 __device__ __forceinline__ long long block_max_ll(long long v, long long *red) {
 #pragma unroll
@@ -309,11 +313,14 @@ __global__ __launch_bounds__(PLAN_THREADS) void k_niche_plan(BatchView bv) {
         // keys of the owned members of T (group 0 when it is the only one)
         u64 kc[PLAN_PER];
 #pragma unroll
-        for (int q = 0; q < PLAN_PER; ++q) {
-            const int j = q * PLAN_THREADS + tid;
-            kc[q] = 0ull;
-            if (!listed && groups == 1 && j < H && cc[q] > 0 && rc[q] <= Ls && Ls < rc[q] + cc[q])
-                kc[q] = tie_key(seed, 1u, (unsigned)j, (unsigned)Ls);
+        for (int q = 0; q < PLAN_PER; ++q) kc[q] = 0ull;
+        if (!listed && groups == 1) {  // uniform: no key hashed when T is listed
+#pragma unroll
+            for (int q = 0; q < PLAN_PER; ++q) {
+                const int j = q * PLAN_THREADS + tid;
+                if (j < H && cc[q] > 0 && rc[q] <= Ls && Ls < rc[q] + cc[q])
+                    kc[q] = tie_key(seed, 1u, (unsigned)j, (unsigned)Ls);
+            }
         }
         // calls BODY with `key` for every key of T owned by this thread
 #define PLAN_KEYS(BODY)                                                                       \
@@ -341,17 +348,28 @@ __global__ __launch_bounds__(PLAN_THREADS) void k_niche_plan(BatchView bv) {
         u64 pmask = 0;
         int need = r;
         int left = (int)tsize;  // keys matching the prefix
-        if (listed && ntk <= PLAN_THREADS) {
+        if (listed && ntk > 0 && ntk <= PLAN_COUNT_MAX) {
             // few keys: each key's rank is the number of smaller ones (keys
             // of distinct references differ); the one of rank r - 1 is the
-            // threshold, found in one pass instead of radix passes
-            if (tid < ntk) {
-                const u64 mine = t_key[tid];
-                int rank = 0;
+            // threshold, found in one pass instead of radix passes. Key e's
+            // comparisons are split into `slices` ranges over all threads,
+            // the partial counts summed in LDS (the bins are free here).
+            const int slices = PLAN_THREADS / ntk;
+            const int chunk = (ntk + slices - 1) / slices;
+            const int sl = tid / ntk, e = tid - sl * ntk;
+            unsigned *rank_of = hist;
+            if (tid < ntk) rank_of[tid] = 0;
+            lds_barrier();
+            if (sl < slices) {
+                const u64 mine = t_key[e];
+                const int v0 = sl * chunk, v1 = min(ntk, v0 + chunk);
+                unsigned part = 0;
 #pragma unroll 8
-                for (int v = 0; v < ntk; ++v) rank += t_key[v] < mine;
-                if (rank == r - 1) cand_thr[0] = mine;
+                for (int v = v0; v < v1; ++v) part += t_key[v] < mine;
+                if (part) atomicAdd(&rank_of[e], part);
             }
+            lds_barrier();
+            if (tid < ntk && rank_of[tid] == (unsigned)(r - 1)) cand_thr[0] = t_key[tid];
             lds_barrier();
             prefix = uniform(cand_thr[0]);
             pmask = ~0ull;
@@ -427,14 +445,20 @@ __global__ __launch_bounds__(PLAN_THREADS) void k_niche_plan(BatchView bv) {
     }
     // per-reference pick counts: up to level L*, plus one at L* for the r
     // least keys of T (members of a listed T are written from the list)
-    PLAN_FOR({
-        const bool in_t = r > 0 && cj > 0 && rj <= Ls && Ls < rj + cj;
-        if (!(listed && in_t)) {
+    if (listed) {
+        // members of T are written from the list below; no key is hashed here
+        PLAN_FOR({
+            const bool in_t = cj > 0 && rj <= Ls && Ls < rj + cj;
+            if (!in_t) tpick[j] = (int)min((long long)cj, max(0ll, (long long)Ls - rj));
+        })
+    } else {
+        PLAN_FOR({
+            const bool in_t = r > 0 && cj > 0 && rj <= Ls && Ls < rj + cj;
             int t = (int)min((long long)cj, max(0ll, (long long)Ls - rj));
             if (in_t && (every || tie_key(seed, 1u, (unsigned)j, (unsigned)Ls) <= prefix)) t += 1;
             tpick[j] = t;
-        }
-    })
+        })
+    }
 #undef PLAN_FOR
     for (int e = tid; e < ntk; e += PLAN_THREADS)
         tpick[t_ref[e]] = Ls - t_rho[e] + (t_key[e] <= prefix ? 1 : 0);
