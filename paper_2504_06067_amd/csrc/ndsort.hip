@@ -386,8 +386,7 @@ __device__ __forceinline__ void dom_tile_ord(std::integer_sequence<int, Gs...>,
 // scalar cache.
 template <int MO>
 __global__ __launch_bounds__(256) void k_dominance(BatchView bv, int gs, int gn,
-                                                    long long item0, long long n_items,
-                                                    int counts) {
+                                                    long long item0, long long n_items) {
     const int lane = lane_id();
     const long long gitem = uniform(item0 + (long long)blockIdx.x * 4 + (threadIdx.x >> 6));
     if (gitem >= item0 + n_items) return;
@@ -437,10 +436,10 @@ __global__ __launch_bounds__(256) void k_dominance(BatchView bv, int gs, int gn,
                 const u64 B = ((u64)b_hi << 32) | b_lo;
                 mask[(size_t)jb * Mp + (size_t)ib * 64 + lane] = B;
                 const int c = __popcll(B);
-                if (counts && c) atomicAdd(&nd[ib * 64 + lane], c);
+                if (c) atomicAdd(&nd[ib * 64 + lane], c);
             }
         }
-        if (counts && cnt_j) atomicAdd(&nd[jglob], cnt_j);
+        if (cnt_j) atomicAdd(&nd[jglob], cnt_j);
         t = tri(jb) + ib1;
         ++jb;
         ib = 0;
@@ -462,8 +461,7 @@ __global__ __launch_bounds__(256) void k_dominance(BatchView bv, int gs, int gn,
 constexpr int DW_KC = 32;
 
 __global__ __launch_bounds__(256) void k_dominance_wide(BatchView bv, int gs, int gn,
-                                                         long long item0, long long n_items,
-                                                         int counts) {
+                                                         long long item0, long long n_items) {
     __shared__ float s_col[4][64][DW_KC + 1];  // padded rows: conflict-free staging
     __shared__ u64 s_lt[4][64], s_gt[4][64];
     const int lane = lane_id();
@@ -526,13 +524,13 @@ __global__ __launch_bounds__(256) void k_dominance_wide(BatchView bv, int gs, in
         }
         mask[(size_t)ib * Mp + (size_t)jb * 64 + lane] = A;
         const int cnt_j = __popcll(A);
-        if (counts && cnt_j) atomicAdd(&nd[jb * 64 + lane], cnt_j);
+        if (cnt_j) atomicAdd(&nd[jb * 64 + lane], cnt_j);
         if (ib != jb) {
             // column point i = lane: its dominators in row block jb
             const u64 B = lane < ncol ? (s_gt[wv][lane] & ~s_lt[wv][lane] & rowvalid) : 0ull;
             mask[(size_t)jb * Mp + (size_t)ib * 64 + lane] = B;
             const int c = __popcll(B);
-            if (counts && c) atomicAdd(&nd[ib * 64 + lane], c);
+            if (c) atomicAdd(&nd[ib * 64 + lane], c);
         }
         __builtin_amdgcn_wave_barrier();  // LDS words are reused by the next tile
         ++t;
@@ -802,37 +800,6 @@ __device__ void peel_pair(CInst &I, int k, int c0, int c1, PeelShared &sh, const
     lds_barrier();  // the shared partial sums are free again
 }
 
-// Dominator counts of chunk c (popcounts over its whole column, streamed
-// once) into the counts in global memory, for a chunk beyond the cache slots
-// of a peel whose dominance launch did not count. All waves take part.
-__device__ void count_streamed(CInst &I, int c, PeelShared &sh) {
-    const int lane = lane_id();
-    const int wv = uniform((int)(threadIdx.x >> 6));
-    const int we = uniform(I.P.col_end[c]);  // zero (and unwritten) words from here on
-    const size_t Mp = (size_t)I.Mp;
-    const u64 *__restrict__ src = I.P.mask + (size_t)c * 64 + lane;
-    int acc = 0;
-    for (int w0 = wv; w0 < we; w0 += PEEL_WAVES * 4) {
-        u64 x[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int w = w0 + q * PEEL_WAVES;
-            x[q] = w < we ? src[(size_t)w * Mp] : 0ull;
-        }
-#pragma unroll
-        for (int q = 0; q < 4; ++q) acc += __popcll(x[q]);
-    }
-    sh.part[0][wv][lane] = acc;
-    lds_barrier();
-    if (wv == 0) {
-        int cnt = 0;
-#pragma unroll
-        for (int v = 0; v < PEEL_WAVES; ++v) cnt += sh.part[0][v][lane];
-        I.P.nd[c * 64 + lane] = cnt;
-    }
-    lds_barrier();  // the shared partial sums are free again
-}
-
 // A chunk whose column is streamed.
 template <int BATCH>
 __device__ __forceinline__ void peel_chunk(CInst &I, int k, int c, int own, PeelShared &sh) {
@@ -917,12 +884,12 @@ __global__ __launch_bounds__(64 * PEEL_WAVES) void k_peel(BatchView bv, int c0, 
             sh.own_cum[1][nown] = 0;
         }
     };
-    // Streamed columns: front 0 of each chunk at its claim, from the counts
-    // fused into the dominance kernel. Cached columns: up to PEEL_CACHE_SLOTS
-    // claims, then front 0 of those from counts over their loaded columns;
-    // then, while chunks are left, further claims streamed as above but
-    // counting over their column first. Every running workgroup claims until
-    // none is left, so every chunk has a running owner.
+    // Front 0 of every chunk comes from the counts fused into the dominance
+    // kernel. Streamed columns: front 0 of each chunk at its claim. Cached
+    // columns: up to PEEL_CACHE_SLOTS claims, front 0 of those, then their
+    // column loads; then, while chunks are left, further claims streamed as
+    // above. Every running workgroup claims until none is left, so every
+    // chunk has a running owner.
     bool dry = false;
     constexpr int FIRST_CAP = Q > 0 ? PEEL_CACHE_SLOTS : PEEL_OWN_CAP;
     while (nown < FIRST_CAP) {
@@ -941,34 +908,41 @@ __global__ __launch_bounds__(64 * PEEL_WAVES) void k_peel(BatchView bv, int c0, 
     u64 col0[Q > 0 ? Q : 1], col1[Q > 0 ? Q : 1];
     if constexpr (Q > 0) {
         if (nown > 0) {
-            const int b0 = uniform(sh.own_b[0]), c0 = uniform(sh.own_c[0]);
-            const int b1 = nown > 1 ? uniform(sh.own_b[1]) : b0;
-            const int c1 = nown > 1 ? uniform(sh.own_c[1]) : c0;
-            load_column<Q>(bv.tab[b0], c0, col0);
-            if (nown > 1) load_column<Q>(bv.tab[b1], c1, col1);
-            int a0 = 0, a1 = 0;
-#pragma unroll
-            for (int q = 0; q < Q; ++q) {
-                a0 += __popcll(col0[q]);
-                a1 += nown > 1 ? __popcll(col1[q]) : 0;
-            }
-            sh.part[0][wv][lane] = a0;
-            sh.part[1][wv][lane] = a1;
-            lds_barrier();
+            // front 0 of the cached chunks from the counts fused into the
+            // dominance kernel, published before their columns arrive (the
+            // loads overlap the wait for the other chunks' front 0)
             if (wv < nown) {  // waves 0 and 1: slots 0 and 1
                 const int slot = wv;
-                CInst &I = bv.tab[slot ? b1 : b0];
-                const int c = slot ? c1 : c0;
-                int cnt = 0;
-#pragma unroll
-                for (int v = 0; v < PEEL_WAVES; ++v) cnt += sh.part[slot][v][lane];
+                CInst &I = bv.tab[uniform(sh.own_b[slot])];
+                const int c = uniform(sh.own_c[slot]);
+                const int cnt = I.P.nd[c * 64 + lane];
                 sh.cleft[slot][lane] = cnt;
                 const int valid = I.M - c * 64;
                 const u64 aw = valid >= 64 ? ~0ull : ((1ull << valid) - 1);
                 publish(I, 0, c, slot, aw, aw & ballot(cnt == 0), sh);
             }
-            lds_barrier();  // the shared partial sums are free again
         }
+        // Are chunks left to claim? Wave 0 reads the shard counters (one
+        // round trip) before its column loads, so waiting for them does not
+        // wait for the columns, and the check overlaps the loads.
+        u64 n_l = 0;
+        if (!dry && wv == 0 && lane < TICKET_SHARDS)
+            n_l = load_relaxed(&bv.ticket[lane * TICKET_STRIDE + tw]);
+        if (nown > 0) {
+            const int b0 = uniform(sh.own_b[0]), c0 = uniform(sh.own_c[0]);
+            load_column<Q>(bv.tab[b0], c0, col0);
+            if (nown > 1) load_column<Q>(bv.tab[uniform(sh.own_b[1])], uniform(sh.own_c[1]), col1);
+        }
+        if (!dry && wv == 0) {
+            const u64 avail = ballot(lane < TICKET_SHARDS &&
+                                     (u64)lane + (u64)TICKET_SHARDS * n_l < (u64)nchunk);
+            if (lane == 0) sh.val2 = avail;
+        }
+        lds_barrier();  // the published state and the check are visible to every wave
+        // (counters only grow: when no shard has a ticket left, every chunk
+        // has an owner)
+        if (!dry && uniform(sh.val2) == 0) dry = true;
+        // chunks beyond the cache slots: streamed, front 0 at the claim
         while (!dry && nown < PEEL_OWN_CAP) {
             u64 t2;
             const u64 t = claim(PEEL_OWN_CAP - nown >= 2 ? 2 : 1, t2);
@@ -977,7 +951,6 @@ __global__ __launch_bounds__(64 * PEEL_WAVES) void k_peel(BatchView bv, int c0, 
                 if (tc >= (u64)nchunk) break;
                 int b, c;
                 own(tc, b, c);
-                count_streamed(bv.tab[b], c, sh);
                 peel_chunk<BATCH>(bv.tab[b], 0, c, nown, sh);
                 ++nown;
             }
@@ -1056,9 +1029,8 @@ hipError_t launch_prepare(const HostPlan &hp, const BatchView &bv, bool init_don
 // W = max_W: columns stay in registers (returns the per-wave cache size) when
 // every column fits a cache and two cached chunks per compute unit hold all
 // chunks (one workgroup per compute unit at that register use); otherwise
-// they are streamed (returns 0). A peel with cached columns counts dominators
-// from them; a streamed one takes the counts fused into the dominance kernel
-// (its front 0 then needs no pass over the matrix).
+// they are streamed (returns 0). Either way front 0 comes from the counts
+// fused into the dominance kernel (no pass over the matrix before it).
 static int peel_cache(int nchunk, int max_W, int cus) {
     if (nchunk > PEEL_CACHE_SLOTS * cus) return 0;
     for (int c : {16, 24, 32, 40, 48})
@@ -1082,16 +1054,14 @@ static void launch_peel(const BatchView &bv, int q, int c0, int nchunk, int tw, 
     }
 }
 
-static void launch_dominance(const HostPlan &hp, const BatchView &bv, int g, bool counts,
-                             hipStream_t s) {
+static void launch_dominance(const HostPlan &hp, const BatchView &bv, int g, hipStream_t s) {
     const int gs = hp.grp_start[g], gn = hp.grp_start[g + 1] - gs;
     const long long item0 = hp.grp_dom[g], n_items = hp.grp_dom[g + 1] - item0;
     const unsigned blocks = (unsigned)((n_items + 3) / 4);
-    const int cf = counts ? 1 : 0;
 #define NSGA3_DOM_CASE(MO)                                                                       \
     case MO:                                                                                     \
         NSGA3_LAUNCH("dominance", k_dominance<MO>, dim3(blocks), dim3(256), 0, s, bv, gs, gn,   \
-                     item0, n_items, cf);                                                        \
+                     item0, n_items);                                                            \
         break;
     switch (hp.grp_m[g]) {
         NSGA3_DOM_CASE(2) NSGA3_DOM_CASE(3) NSGA3_DOM_CASE(4) NSGA3_DOM_CASE(5)
@@ -1100,7 +1070,7 @@ static void launch_dominance(const HostPlan &hp, const BatchView &bv, int g, boo
         NSGA3_DOM_CASE(14) NSGA3_DOM_CASE(15) NSGA3_DOM_CASE(16)
         default:
             NSGA3_LAUNCH("dominance", k_dominance_wide, dim3(blocks), dim3(256), 0, s, bv, gs, gn,
-                         item0, n_items, cf);
+                         item0, n_items);
             break;
     }
 #undef NSGA3_DOM_CASE
@@ -1172,7 +1142,7 @@ hipError_t launch_nd_sort(const HostPlan &hp, const BatchView &bv, hipStream_t s
             for (int g = 0; g < hp.ngroups && e == hipSuccess; ++g) {
                 const int c0 = hp.grp_chunk[g], nc = hp.grp_chunk[g + 1] - c0;
                 const int q = peel_cache(nc, hp.grp_max_W[g], cus);
-                launch_dominance(hp, bv, g, q == 0, s);
+                launch_dominance(hp, bv, g, s);
                 e = hipEventRecord(p->ev[g], s);
                 if (e == hipSuccess) e = hipStreamWaitEvent(p->side, p->ev[g], 0);
                 if (e == hipSuccess) launch_peel(bv, q, c0, nc, g, cus, PEEL_PIPE_PER_CU, p->side);
@@ -1188,7 +1158,7 @@ hipError_t launch_nd_sort(const HostPlan &hp, const BatchView &bv, hipStream_t s
         }
     }
     const int q = peel_cache(hp.nchunk, hp.max_W, cus);
-    for (int g = 0; g < hp.ngroups; ++g) launch_dominance(hp, bv, g, q == 0, s);
+    for (int g = 0; g < hp.ngroups; ++g) launch_dominance(hp, bv, g, s);
     launch_peel(bv, q, 0, hp.nchunk, 0, cus, 3, s);
     return hipGetLastError();
 }
