@@ -360,9 +360,15 @@ static hipError_t enqueue(Plan &p, char *ws, hipStream_t s) {
     }
     if (e == hipSuccess) e = launch_prepare(p.hp, p.bv, fused, s);
     const int run = p.bv.run;
-    if (e == hipSuccess && (run & RUN_ND)) e = launch_nd_sort(p.hp, p.bv, s);
-    if (e == hipSuccess && (run & RUN_NORM)) e = launch_normalize(p.hp, p.bv, s);
-    if (e == hipSuccess && (run & RUN_ASSOC)) e = launch_associate(p.hp, p.bv, s);
+    // a whole selection whose m-groups all take the one-pass normalization
+    // may run each group's normalization and association sweep right after
+    // its peel
+    bool through = (run & RUN_ND) && (run & RUN_NORM) && (run & RUN_ASSOC);
+    for (int g = 0; g < p.hp.ngroups && through; ++g) through = p.hp.grp_m[g] <= NARROW_M;
+    if (e == hipSuccess && (run & RUN_ND)) e = launch_nd_sort(p.hp, p.bv, s, &through);
+    else through = false;
+    if (e == hipSuccess && (run & RUN_NORM) && !through) e = launch_normalize(p.hp, p.bv, s);
+    if (e == hipSuccess && (run & RUN_ASSOC)) e = launch_associate(p.hp, p.bv, s, through);
     if (e == hipSuccess && (run & RUN_NICHE)) e = launch_niche(p.hp, p.bv, s);
     return e;
 }

@@ -216,30 +216,36 @@ __global__ __launch_bounds__(256) void k_associate_wide(BatchView bv, int gs, in
     assoc_merge(I, x, in, h0 < h1, best, bj);
 }
 
-hipError_t launch_associate(const HostPlan &hp, const BatchView &bv, hipStream_t s) {
-    const unsigned pblocks = (unsigned)(hp.npt / 256);
-    if (!(bv.run & RUN_NORM))
-        NSGA3_LAUNCH("assoc_list", k_assoc_list, dim3(pblocks), dim3(256), 0, s, bv);
-    for (int g = 0; g < hp.ngroups; ++g) {
-        const int gs = hp.grp_start[g], gn = hp.grp_start[g + 1] - gs;
-        const long long item0 = hp.grp_asc[g], n_items = hp.grp_asc[g + 1] - item0;
-        const unsigned blocks = (unsigned)((n_items + 3) / 4);
+// The association sweep of group g (instances of one m).
+void launch_associate_group(const HostPlan &hp, const BatchView &bv, int g, hipStream_t s) {
+    const int gs = hp.grp_start[g], gn = hp.grp_start[g + 1] - gs;
+    const long long item0 = hp.grp_asc[g], n_items = hp.grp_asc[g + 1] - item0;
+    const unsigned blocks = (unsigned)((n_items + 3) / 4);
 #define NSGA3_ASSOC_CASE(MO)                                                                   \
     case MO:                                                                                   \
         NSGA3_LAUNCH("associate", k_associate<MO>, dim3(blocks), dim3(256), 0, s, bv, gs, gn,  \
                      item0, n_items);                                                          \
         break;
-        switch (hp.grp_m[g]) {
-            NSGA3_ASSOC_CASE(2) NSGA3_ASSOC_CASE(3) NSGA3_ASSOC_CASE(4) NSGA3_ASSOC_CASE(5)
-            NSGA3_ASSOC_CASE(6) NSGA3_ASSOC_CASE(7) NSGA3_ASSOC_CASE(8) NSGA3_ASSOC_CASE(9)
-            NSGA3_ASSOC_CASE(10) NSGA3_ASSOC_CASE(11) NSGA3_ASSOC_CASE(12) NSGA3_ASSOC_CASE(13)
-            NSGA3_ASSOC_CASE(14) NSGA3_ASSOC_CASE(15) NSGA3_ASSOC_CASE(16)
-            default:
-                NSGA3_LAUNCH("associate", k_associate_wide, dim3(blocks), dim3(256), 0, s, bv, gs,
-                             gn, item0, n_items);
-                break;
-        }
+    switch (hp.grp_m[g]) {
+        NSGA3_ASSOC_CASE(2) NSGA3_ASSOC_CASE(3) NSGA3_ASSOC_CASE(4) NSGA3_ASSOC_CASE(5)
+        NSGA3_ASSOC_CASE(6) NSGA3_ASSOC_CASE(7) NSGA3_ASSOC_CASE(8) NSGA3_ASSOC_CASE(9)
+        NSGA3_ASSOC_CASE(10) NSGA3_ASSOC_CASE(11) NSGA3_ASSOC_CASE(12) NSGA3_ASSOC_CASE(13)
+        NSGA3_ASSOC_CASE(14) NSGA3_ASSOC_CASE(15) NSGA3_ASSOC_CASE(16)
+        default:
+            NSGA3_LAUNCH("associate", k_associate_wide, dim3(blocks), dim3(256), 0, s, bv, gs, gn,
+                         item0, n_items);
+            break;
+    }
 #undef NSGA3_ASSOC_CASE
+}
+
+hipError_t launch_associate(const HostPlan &hp, const BatchView &bv, hipStream_t s,
+                            bool sweeps_done) {
+    const unsigned pblocks = (unsigned)(hp.npt / 256);
+    if (!sweeps_done) {
+        if (!(bv.run & RUN_NORM))
+            NSGA3_LAUNCH("assoc_list", k_assoc_list, dim3(pblocks), dim3(256), 0, s, bv);
+        for (int g = 0; g < hp.ngroups; ++g) launch_associate_group(hp, bv, g, s);
     }
     NSGA3_LAUNCH("assoc_final", k_assoc_final, dim3(pblocks), dim3(256), 0, s, bv);
     return hipGetLastError();

@@ -1133,7 +1133,7 @@ static PeelPipe *pipe_for(hipStream_t s) {
     return &p;
 }
 
-hipError_t launch_nd_sort(const HostPlan &hp, const BatchView &bv, hipStream_t s) {
+hipError_t launch_nd_sort(const HostPlan &hp, const BatchView &bv, hipStream_t s, bool *through) {
     const int cus = device_info().cus;
     if (hp.B > 1 && hp.ngroups > 1 && hp.ngroups <= PEEL_PIPE_GROUPS) {
         std::lock_guard<std::mutex> lock(g_pipe_mu);
@@ -1145,7 +1145,15 @@ hipError_t launch_nd_sort(const HostPlan &hp, const BatchView &bv, hipStream_t s
                 launch_dominance(hp, bv, g, s);
                 e = hipEventRecord(p->ev[g], s);
                 if (e == hipSuccess) e = hipStreamWaitEvent(p->side, p->ev[g], 0);
-                if (e == hipSuccess) launch_peel(bv, q, c0, nc, g, cus, PEEL_PIPE_PER_CU, p->side);
+                if (e == hipSuccess) {
+                    launch_peel(bv, q, c0, nc, g, cus, PEEL_PIPE_PER_CU, p->side);
+                    // the group's normalization and association sweep need
+                    // only its own ranks (their grids skip other groups)
+                    if (*through) {
+                        launch_norm_fused_group(hp, bv, g, p->side);
+                        launch_associate_group(hp, bv, g, p->side);
+                    }
+                }
             }
             // join even after an error, so that the side stream leaves no
             // open fork in a capture
@@ -1157,6 +1165,7 @@ hipError_t launch_nd_sort(const HostPlan &hp, const BatchView &bv, hipStream_t s
             return e == hipSuccess ? hipGetLastError() : e;
         }
     }
+    *through = false;
     const int q = peel_cache(hp.nchunk, hp.max_W, cus);
     for (int g = 0; g < hp.ngroups; ++g) launch_dominance(hp, bv, g, s);
     launch_peel(bv, q, 0, hp.nchunk, 0, cus, 3, s);

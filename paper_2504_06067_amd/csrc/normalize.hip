@@ -430,6 +430,24 @@ __global__ __launch_bounds__(256) void k_norm_apply(BatchView bv) {
         I.Fn[(size_t)x * m + k] = (I.F[(size_t)x * m + k] - ctrl->zf[k]) * ctrl->recip[k];
 }
 
+// The one-pass normalization of group g (m <= NARROW_M) of a whole selection.
+void launch_norm_fused_group(const HostPlan &hp, const BatchView &bv, int g, hipStream_t s) {
+    const unsigned pblocks = (unsigned)(hp.npt / 256);
+#define NSGA3_FUSED_CASE(MO)                                                                   \
+    case MO:                                                                                   \
+        NSGA3_LAUNCH("norm_fused", k_norm_fused<MO>, dim3(pblocks), dim3(256), 0, s, bv);      \
+        break;
+    switch (hp.grp_m[g]) {
+        NSGA3_FUSED_CASE(2) NSGA3_FUSED_CASE(3) NSGA3_FUSED_CASE(4) NSGA3_FUSED_CASE(5)
+        NSGA3_FUSED_CASE(6) NSGA3_FUSED_CASE(7) NSGA3_FUSED_CASE(8) NSGA3_FUSED_CASE(9)
+        NSGA3_FUSED_CASE(10) NSGA3_FUSED_CASE(11) NSGA3_FUSED_CASE(12)
+        NSGA3_FUSED_CASE(13) NSGA3_FUSED_CASE(14) NSGA3_FUSED_CASE(15)
+        NSGA3_FUSED_CASE(16)
+        default: break;  // m > NARROW_M: launch_normalize's general kernels
+    }
+#undef NSGA3_FUSED_CASE
+}
+
 hipError_t launch_normalize(const HostPlan &hp, const BatchView &bv, hipStream_t s) {
     const unsigned pblocks = (unsigned)(hp.npt / 256);
     bool wide = false;
@@ -438,21 +456,7 @@ hipError_t launch_normalize(const HostPlan &hp, const BatchView &bv, hipStream_t
     if (select) {
         // a whole selection: one pass for m <= NARROW_M (the ideal point came
         // with the preparation), Fn formed inside the association sweep
-        for (int g = 0; g < hp.ngroups; ++g) {
-#define NSGA3_FUSED_CASE(MO)                                                                   \
-    case MO:                                                                                   \
-        NSGA3_LAUNCH("norm_fused", k_norm_fused<MO>, dim3(pblocks), dim3(256), 0, s, bv);      \
-        break;
-            switch (hp.grp_m[g]) {
-                NSGA3_FUSED_CASE(2) NSGA3_FUSED_CASE(3) NSGA3_FUSED_CASE(4) NSGA3_FUSED_CASE(5)
-                NSGA3_FUSED_CASE(6) NSGA3_FUSED_CASE(7) NSGA3_FUSED_CASE(8) NSGA3_FUSED_CASE(9)
-                NSGA3_FUSED_CASE(10) NSGA3_FUSED_CASE(11) NSGA3_FUSED_CASE(12)
-                NSGA3_FUSED_CASE(13) NSGA3_FUSED_CASE(14) NSGA3_FUSED_CASE(15)
-                NSGA3_FUSED_CASE(16)
-                default: break;  // m > NARROW_M: below
-            }
-#undef NSGA3_FUSED_CASE
-        }
+        for (int g = 0; g < hp.ngroups; ++g) launch_norm_fused_group(hp, bv, g, s);
         if (!wide) return hipGetLastError();
     }
     // list, ideal point and maxima over S_t (for m > NARROW_M only, in a

@@ -418,9 +418,17 @@ hipError_t launch_evolve(const nsga3_evolve_slot *slots, int B, char *ws, hipStr
 
 // init_done: the instance was initialized with the header copy (k_blob_init).
 hipError_t launch_prepare(const HostPlan &hp, const BatchView &bv, bool init_done, hipStream_t s);
-hipError_t launch_nd_sort(const HostPlan &hp, const BatchView &bv, hipStream_t s);
+// *through: in: the normalization and association sweeps may be pipelined
+// with the peel (a whole selection whose groups all have m <= NARROW_M);
+// out: they were (launch_normalize is then skipped and launch_associate only
+// finishes).
+hipError_t launch_nd_sort(const HostPlan &hp, const BatchView &bv, hipStream_t s, bool *through);
 hipError_t launch_normalize(const HostPlan &hp, const BatchView &bv, hipStream_t s);
-hipError_t launch_associate(const HostPlan &hp, const BatchView &bv, hipStream_t s);
+// sweeps_done: the per-group sweeps already ran (pipelined with the peel).
+hipError_t launch_associate(const HostPlan &hp, const BatchView &bv, hipStream_t s,
+                            bool sweeps_done);
+void launch_norm_fused_group(const HostPlan &hp, const BatchView &bv, int g, hipStream_t s);
+void launch_associate_group(const HostPlan &hp, const BatchView &bv, int g, hipStream_t s);
 hipError_t launch_niche(const HostPlan &hp, const BatchView &bv, hipStream_t s);
 
 // One-workgroup selection of a small instance (tiny.hip): whether the shape
