@@ -589,7 +589,7 @@ def plain_steps(inst, dev, steps, warmup, profile=None):
     return dict(wall=wall, step_ms=step_ms, kernels=kern, gpu_out=gpu_out)
 
 
-KERNELS = ("header,prep,place_scatter,dominance,peel,norm_fused,norm_reduce,norm_extreme,associate,assoc_final,"
+KERNELS = ("header,prep,place_scatter,place_gather,dominance,peel,norm_fused,norm_reduce,norm_extreme,associate,assoc_final,"
            "niche_plan,niche_scatter,niche_pick,compact")
 
 

@@ -38,13 +38,17 @@ __global__ __launch_bounds__(256) void k_init(BatchView bv) {
 //   bucket(x) = floor((f_1(x) - lo) * PLACE_BUCKETS / (hi - lo)), clamped,
 // (lo, hi: least and largest f_1 of a strided sample of 256 points), a
 // monotone function of f_1 in float32. k_prep counts the buckets, and
-// k_place_scatter places the points.
+// k_place_scatter places the points (k_place_gather writes large objective
+// copies in position order).
 // A point in a lower bucket has a strictly smaller f_1, so it cannot be
 // dominated by a point of a higher bucket. For a tile whose column block
 // lies wholly in lower buckets than its row block ("ordered") one direction
 // of the relation is known to be empty and the other needs no compare of f_1.
 // Within a bucket the positions follow the order of arrival; ranks do not
 // depend on positions, only the internal matrix does.
+
+// Largest objective copy written by scattered stores (one L2 of an XCD).
+constexpr long long PLACE_SCATTER_BYTES = 4ll << 20;
 
 __device__ __forceinline__ int place_bucket(float x, float lo, float scale) {
     const float t = (x - lo) * scale;
@@ -191,7 +195,9 @@ __global__ __launch_bounds__(256) void k_prep(BatchView bv, int npt) {
 // each point goes to its position: the objective copy (blocks of 64
 // positions, objective-major within a block), the position's point, and the
 // tile bounds of the position's block (from its first and its last point).
-__global__ __launch_bounds__(256) void k_place_scatter(BatchView bv) {
+// copy: the point also writes its objectives at the position (a scattered
+// 4-byte store per objective); otherwise k_place_gather writes the copy.
+__global__ __launch_bounds__(256) void k_place_scatter(BatchView bv, int copy) {
     __shared__ int start[PLACE_BUCKETS + 1];
     __shared__ int wsum[4];
     const Local L = locate(bv.pt_pref, bv.B);
@@ -221,8 +227,10 @@ __global__ __launch_bounds__(256) void k_place_scatter(BatchView bv) {
         const int b = (int)(key >> PLACE_RANK_BITS);
         const int pos = start[b] + (int)(key & ((1u << PLACE_RANK_BITS) - 1u));
         I.P.perm[pos] = j;
-        float *dst = I.P.ft + (size_t)(pos >> 6) * m * 64 + (pos & 63);
-        for (int k = 0; k < m; ++k) dst[k * 64] = I.F[(size_t)j * m + k];
+        if (copy) {
+            float *dst = I.P.ft + (size_t)(pos >> 6) * m * 64 + (pos & 63);
+            for (int k = 0; k < m; ++k) dst[k * 64] = I.F[(size_t)j * m + k];
+        }
         // tiles (ib, jb) with every point of ib in a lower bucket than the
         // first point of jb: ib below the block of that bucket's start
         if ((pos & 63) == 0) I.P.row_ord[pos >> 6] = start[b] >> 6;
@@ -230,6 +238,22 @@ __global__ __launch_bounds__(256) void k_place_scatter(BatchView bv) {
         // bucket of c's last point are zero
         if ((pos & 63) == 63 || pos == M - 1) I.P.col_end[pos >> 6] = (start[b + 1] + 63) >> 6;
     }
+}
+
+// The objective copy in position order: each position reads its point's
+// row of F (a gather) and the 64 positions of a block write each objective's
+// 256 bytes together. For copies larger than the L2, where scattered 4-byte
+// stores cost a partial-line write each. Grid: all instances' padded points
+// (as positions).
+__global__ __launch_bounds__(256) void k_place_gather(BatchView bv) {
+    const Local L = locate(bv.pt_pref, bv.B);
+    CInst &I = bv.tab[L.b];
+    const int pos = L.i, M = I.M, m = I.m;
+    if (pos >= M) return;
+    const int j = I.P.perm[pos];
+    float *dst = I.P.ft + (size_t)(pos >> 6) * m * 64 + (pos & 63);
+    const float *src = I.F + (size_t)j * m;
+    for (int k = 0; k < m; ++k) dst[k * 64] = src[k];
 }
 
 // Lane R of `old` takes the wave-uniform value v.
@@ -1020,8 +1044,16 @@ __global__ __launch_bounds__(64 * PEEL_WAVES) void k_peel(BatchView bv, int c0, 
 hipError_t launch_prepare(const HostPlan &hp, const BatchView &bv, bool init_done, hipStream_t s) {
     if (!init_done) NSGA3_LAUNCH("init", k_init, dim3(hp.B), dim3(256), 0, s, bv);
     NSGA3_LAUNCH("prep", k_prep, dim3((hp.npt + hp.nref) / 256), dim3(256), 0, s, bv, hp.npt);
-    if (bv.run & RUN_ND)
-        NSGA3_LAUNCH("place_scatter", k_place_scatter, dim3(hp.npt / 256), dim3(256), 0, s, bv);
+    if (bv.run & RUN_ND) {
+        // the objective copy by scattered stores while it fits the L2, else
+        // by a gather in position order
+        const long long copy_bytes = (long long)hp.npt * hp.grp_m[hp.ngroups - 1] * 4;
+        const int scatter = copy_bytes <= PLACE_SCATTER_BYTES ? 1 : 0;
+        NSGA3_LAUNCH("place_scatter", k_place_scatter, dim3(hp.npt / 256), dim3(256), 0, s, bv,
+                     scatter);
+        if (!scatter)
+            NSGA3_LAUNCH("place_gather", k_place_gather, dim3(hp.npt / 256), dim3(256), 0, s, bv);
+    }
     return hipGetLastError();
 }
 
