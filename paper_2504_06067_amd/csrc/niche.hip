@@ -41,6 +41,8 @@ __device__ __forceinline__ u64 read_lane_u64(u64 x, int L) {
     return ((u64)hi << 32) | lo;
 }
 constexpr int PICK_CAP = 2048;          // segment length kept in LDS by one wave
+constexpr int PICK_DECODE_MAX = 256;    // most picks of a reference decoded in parallel
+constexpr int PICK_DECODE_MIN = 8;      // fewer picks: the serial chain is shorter
 
 // Stage call only (a whole selection counts in the association's final pass).
 __global__ __launch_bounds__(256) void k_niche_count(BatchView bv) {
@@ -585,6 +587,67 @@ __device__ __forceinline__ void pick_sorted(int *buf, u64 *rem, int c, int t, in
     };
     wave_sort(buf, c);
     const int nw = (c + 63) / 64;
+    if (t >= PICK_DECODE_MIN && t <= PICK_DECODE_MAX) {
+        // Every pick's rank among the candidates still remaining when it is
+        // made is known in advance: the nearest candidate's position at level
+        // 0, else key(seed, 2, j, L) mod (c - p) for pick p at level L. The
+        // ranks form a Lehmer code, decoded for all picks at once (one per
+        // lane): pick i's position is its rank, raised by one for each
+        // earlier pick j (taken from i - 1 down to 0) whose rank is at most
+        // the running value (re-inserting pick j at its rank shifts the
+        // later ranks by one).
+        int pos_near = 0;
+        if (rj == 0) {
+            u64 best = ~0ull;
+#pragma unroll 4
+            for (int i = lane; i < c; i += 64) {
+                const int x = buf[i];
+                const u64 k = ((u64)__float_as_uint(dist[x]) << 32) | (unsigned)i;
+                best = k < best ? k : best;
+            }
+            pos_near = (int)(unsigned)(wave_min_u64(best) & 0xffffffffull);
+        }
+        constexpr int NB = PICK_DECODE_MAX / 64;
+        int kk[NB];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            const int p = b * 64 + lane;
+            kk[b] = 0;
+            if (b * 64 < t && p < t)  // (the first test is uniform)
+                kk[b] = rj + p == 0 ? pos_near
+                                    : (int)(tie_key(seed, 2u, (unsigned)j, (unsigned)(rj + p)) %
+                                            (u64)(c - p));
+        }
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            if (b * 64 >= t) break;  // uniform
+            int r = kk[b];
+#pragma unroll
+            for (int q = 63; q >= 0; --q) {
+                const int kq = __builtin_amdgcn_readlane(kk[b], q);
+                r += (q < lane && kq <= r) ? 1 : 0;
+            }
+#pragma unroll
+            for (int b2 = b - 1; b2 >= 0; --b2) {
+#pragma unroll
+                for (int q = 63; q >= 0; --q) {
+                    const int kq = __builtin_amdgcn_readlane(kk[b2], q);
+                    r += kq <= r ? 1 : 0;
+                }
+            }
+            const int n = min(64, t - b * 64);
+            if (lane < n && r < c) {
+                const int x = buf[r];
+                if (ORDER) {
+                    qrow[b * 64 + lane] = x;
+                } else {
+                    picked[x] = 1;
+                    atomicAdd(&tcnt[x / COMPACT_TILE], 1);
+                }
+            }
+        }
+        return;
+    }
     if (nw <= 64) {
         // Up to 4096 candidates: lane w holds word w of the remaining set in a
         // register, and the pick ranks of 64 levels at a time are computed one
@@ -596,6 +659,23 @@ __device__ __forceinline__ void pick_sorted(int *buf, u64 *rem, int c, int t, in
         // after every removal (no scan per pick)
         int excl = wave_incl_scan(own) - own;
         int kk_lane = 0, kk_base = -1;
+        // the positions picked so far, lane p % 64 holding pick p, written out
+        // 64 at a time in parallel (off the pick-to-pick chain)
+        int mypos = -1, npend = 0;
+        auto flush = [&]() {
+            if (lane < npend) {
+                const int x = buf[mypos];
+                if (ORDER) {
+                    qrow[emitted + lane] = x;
+                } else {
+                    picked[x] = 1;
+                    atomicAdd(&tcnt[x / COMPACT_TILE], 1);
+                }
+            }
+            emitted += npend;
+            npend = 0;
+            mypos = -1;
+        };
         for (int lev = rj; lev < rj + t; ++lev) {
             int pos;
             if (lev == 0) {
@@ -637,8 +717,10 @@ __device__ __forceinline__ void pick_sorted(int *buf, u64 *rem, int c, int t, in
                 own -= 1;
             }
             if (lane > lw) excl -= 1;
-            if (lane == 0) emit(buf[pos]);
+            if (lane == npend) mypos = pos;
+            if (++npend == 64) flush();
         }
+        flush();
         return;
     }
     for (int w = lane; w < nw; w += 64) {
