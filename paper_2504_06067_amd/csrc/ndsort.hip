@@ -2,18 +2,27 @@
 // as a bit-packed dominance matrix followed by front peeling, for a batch of
 // independent instances.
 //
+// The points are first placed in ascending buckets of their first objective
+// (see "point placement" below); the matrix and the peel work on positions.
 // Dominance matrix layout ("word-major"): mask[w * Mp + j] is a 64-bit word
-// whose bit b is set iff point 64*w + b dominates point j. A wave of 64
+// whose bit b is set iff position 64*w + b dominates position j. A wave of 64
 // consecutive j therefore reads or writes 512 contiguous bytes.
 //
 // Kernels:
-//   k_init       per instance: control block, peel counters, front_info
-//   k_prep       points: tile-major objective copy (+inf padding), finiteness,
-//                dominator counts, ranks, the peel's front ring, niche flags;
-//                references: unit directions and their check, niche counters
-//   k_dominance  triangle of 64x64 tiles; both directions from one set of 2m
-//                compares per pair; fused dominator counts
-//   k_peel       fronts of every instance, persistent over all their chunks
+//   k_init           per instance: control block, peel counters, front_info,
+//                    placement counts
+//   k_prep           points: finiteness, +inf padding of the objective copy,
+//                    dominator counts, ranks, the peel's front ring, niche
+//                    flags, placement bucket counts; references: unit
+//                    directions and their check, niche counters
+//   k_place_scatter  each point's position; the objective copy (small copies),
+//                    the position-to-point map, per-block tile bounds
+//   k_place_gather   the objective copy in position order (large copies)
+//   k_dominance      triangle of 64x64 tiles: ordered tiles (one direction,
+//                    m - 1 compares per pair), the rest with both directions
+//                    from one set of 2m compares; fused dominator counts
+//   k_dominance_wide the same for m > NARROW_M, objectives in chunks
+//   k_peel           fronts of every instance, persistent over its chunks
 #include <mutex>
 #include <utility>
 

@@ -19,11 +19,14 @@
 // Kernels:
 //   k_niche_count    rho (fronts < l) and c (front l) per reference (stage
 //                    call; a whole selection counts in the association)
-//   k_niche_plan     one workgroup per instance: CSR offsets, L*, radix select of the r
-//                    least keys, per-reference pick counts t_j
+//   k_niche_plan     one workgroup per instance: CSR offsets, L*, the r-th
+//                    least tag-1 key (counted ranks or radix select),
+//                    per-reference pick counts t_j
 //   k_niche_scatter  members of front l into per-reference segments
 //   k_niche_pick     one wave per reference: sort its segment ascending,
-//                    make its picks with a remaining-set bitmask
+//                    then its picks: decoded all at once from their ranks
+//                    (8 to 256 picks), else one by one with a remaining-set
+//                    bitmask
 //   k_compact        ascending output of S and the picks
 //   k_ct_offsets, k_ct_loop   the paper's cache-tensor loop (A/B baseline)
 #include <limits.h>
