@@ -214,3 +214,30 @@ def test_batched_rejects_bad_arguments():
     rc = nsga3.lib().nsga3_select_batched(bt.arr, bt.B, nsga3._ptr(small), small.numel(),
                                           nsga3._stream(dev))
     assert rc == nsga3.EWORKSPACE
+
+
+def _instances_of_m(ms, seed, M=1200):
+    out = []
+    for b, m in enumerate(ms):
+        rng = np.random.default_rng(seed * 100 + b)
+        F = wl.objectives(rng, M + 64 * b, m, "exp")
+        p = {2: 60, 3: 12, 4: 6, 5: 5, 6: 4, 7: 3, 8: 3, 9: 3, 10: 3, 11: 2}.get(m, 1)
+        Z = wl.das_dennis(m, p)
+        out.append(dict(F=F, Z=Z, M=len(F), m=m, H=len(Z), N=len(F) // 2, seed=seed * 100 + b))
+    return out
+
+
+@pytest.mark.parametrize("ms", [
+    [3, 20, 5, 20, 3],                 # a group with m > 16: peels pipelined, the
+                                       # normalization and association on the caller's stream
+    [2, 3, 4, 5, 6, 7, 8, 9, 10, 11],  # more m-groups than the pipeline takes: one peel
+    [5, 3],                            # two groups
+])
+def test_group_layouts_equal_plain(ms):
+    """Every way the batched call schedules its m-groups gives each instance
+    exactly its plain result."""
+    dev = device()
+    insts = _instances_of_m(ms, 21)
+    got = run_batched(insts, dev)
+    for q, g in zip(insts, got):
+        assert same(g, run_plain(q, dev)), (q["M"], q["m"])
