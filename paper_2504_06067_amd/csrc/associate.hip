@@ -8,14 +8,20 @@
 // reference directions, read through the scalar cache from a
 // structure-of-arrays copy. The distance is formed from the explicit
 // residual r = f - (f . w) w, whose FP32 rounding error scales with ||f||
-// rather than with the (possibly tiny) distance. Slices are merged with a
-// 64-bit atomic min on (d^2 bits << 32 | j): least distance, then least j.
+// rather than with the (possibly tiny) distance. References go in groups of
+// eight reduced by min alone (one compare with the running best per group;
+// the index is recovered once per slice), and up to four objectives the
+// next group's directions load while the current group is computed. Slices
+// are merged with a 64-bit atomic min on (d^2 bits << 32 | j): least
+// distance, then least j.
 //
 // Kernels:
 //   k_assoc_list   (stage call) S_t list, key init, pi = dist = -1 outside S_t
 //   k_associate    the fused sweep; slices merge by a 64-bit atomic min
 //   k_assoc_final  pi and dist from the merged keys; in a whole selection
 //                  also the niche counts rho (fronts < l) and c (front l)
+#include <utility>
+
 #include "steps.h"
 
 namespace nsga3 {
@@ -77,11 +83,73 @@ __global__ __launch_bounds__(256) void k_assoc_final(BatchView bv) {
     }
 }
 
+// References are swept in groups of ASSOC_G: a group's distances are reduced
+// by min alone, and only the group's least distance is compared with the
+// running best (strictly less, so the first group that reaches the final
+// least distance is the one kept). The reference index is then found once:
+// the first j of the kept group whose recomputed distance equals the best,
+// which is the least j at the least distance, as a reference-by-reference
+// strict compare would keep.
+constexpr int ASSOC_G = 8;
+
+// Blocks of ASSOC_BLK references, unrolled, load the directions of the next
+// group through the scalar cache while the current group is computed (two
+// groups of MO x ASSOC_G directions in scalar registers: up to
+// ASSOC_BLK_MAX_M objectives).
+constexpr int ASSOC_BLK = 64;
+constexpr int ASSOC_BLK_MAX_M = 4;
+
+template <int MO>
+struct AssocW {
+    float w[MO][ASSOC_G];
+};
+
+template <int MO>
+__device__ __forceinline__ void assoc_load(const NSGA3_RO float *wn, int Hp, int j,
+                                           AssocW<MO> &g) {
+#pragma unroll
+    for (int k = 0; k < MO; ++k)
+#pragma unroll
+        for (int r = 0; r < ASSOC_G; ++r) g.w[k][r] = wn[(size_t)k * Hp + j + r];
+}
+
+// Group g of a block: scalar loads return in any order, so a wait for the
+// current group would also wait for loads issued after it; the group waits
+// first, then issues the next group's loads, then computes.
+template <int MO, int g>
+__device__ __forceinline__ void assoc_block_group(const float (&f)[MO], const NSGA3_RO float *wn,
+                                                  int Hp, int j, AssocW<MO> &cur, AssocW<MO> &nxt,
+                                                  float &best, int &bg) {
+    __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0)
+    __builtin_amdgcn_sched_barrier(0);
+    if constexpr (g + 1 < ASSOC_BLK / ASSOC_G) assoc_load<MO>(wn, Hp, j + (g + 1) * ASSOC_G, nxt);
+    __builtin_amdgcn_sched_barrier(0);
+    float gm = INFINITY;
+#pragma unroll
+    for (int r = 0; r < ASSOC_G; ++r) {
+        float w[MO];
+#pragma unroll
+        for (int k = 0; k < MO; ++k) w[k] = cur.w[k][r];
+        const float d2 = assoc_d2<MO>(f, (const float *)w, 1, 0);
+        gm = r == 0 ? d2 : fminf(gm, d2);
+    }
+    if (gm < best) { best = gm; bg = j + g * ASSOC_G; }
+    cur = nxt;
+}
+
+template <int MO, int... Gs>
+__device__ __forceinline__ void assoc_block(std::integer_sequence<int, Gs...>, const float (&f)[MO],
+                                            const NSGA3_RO float *wn, int Hp, int j, float &best,
+                                            int &bg) {
+    AssocW<MO> cur, nxt;
+    assoc_load<MO>(wn, Hp, j, cur);
+    (assoc_block_group<MO, Gs>(f, wn, Hp, j, cur, nxt, best, bg), ...);
+}
+
 // Work item = (block of 64 list entries, slice of R references) of one
 // instance of the m-group order[gs .. gs + gn). Items cover the largest
 // possible S_t; items past the actual list length exit at once. The item is
-// wave-uniform, so the unit directions come through the scalar cache; the
-// reference loop is unrolled by four.
+// wave-uniform, so the unit directions come through the scalar cache.
 template <int MO>
 __global__ __launch_bounds__(256) void k_associate(BatchView bv, int gs, int gn, long long item0,
                                                     long long n_items) {
@@ -116,15 +184,30 @@ __global__ __launch_bounds__(256) void k_associate(BatchView bv, int gs, int gn,
     const int h0 = sl * I.R;
     const int h1 = min(h0 + I.R, H);
     float best = INFINITY;
-    int bj = h0;
+    int bg = h0;  // first reference of the kept group (or kept tail reference)
     int j = h0;
-    for (; j + 4 <= h1; j += 4) {
-        assoc_ref<MO>(f, wn, Hp, j, best, bj);
-        assoc_ref<MO>(f, wn, Hp, j + 1, best, bj);
-        assoc_ref<MO>(f, wn, Hp, j + 2, best, bj);
-        assoc_ref<MO>(f, wn, Hp, j + 3, best, bj);
+    if constexpr (MO <= ASSOC_BLK_MAX_M)
+        for (; j + ASSOC_BLK <= h1; j += ASSOC_BLK)
+            assoc_block<MO>(std::make_integer_sequence<int, ASSOC_BLK / ASSOC_G>{}, f, wn, Hp, j,
+                            best, bg);
+    for (; j + ASSOC_G <= h1; j += ASSOC_G) {
+        float gm = assoc_d2<MO>(f, wn, Hp, j);
+#pragma unroll
+        for (int r = 1; r < ASSOC_G; ++r) gm = fminf(gm, assoc_d2<MO>(f, wn, Hp, j + r));
+        if (gm < best) { best = gm; bg = j; }
     }
-    for (; j < h1; ++j) assoc_ref<MO>(f, wn, Hp, j, best, bj);
+    for (; j < h1; ++j) {
+        const float d2 = assoc_d2<MO>(f, wn, Hp, j);
+        if (d2 < best) { best = d2; bg = j; }
+    }
+    // the kept group holds a distance equal to best at or after bg (a tail
+    // reference is its own first match); nothing below infinity keeps h0
+    int bj = bg;
+    if (best < INFINITY) {
+        const int ge = min(bg + ASSOC_G, h1);
+        for (int jj = ge - 1; jj >= bg; --jj)
+            if (assoc_d2<MO>(f, wn, Hp, jj) == best) bj = jj;
+    }
     assoc_merge(I, x, in, h0 < h1, best, bj);
 }
 

@@ -127,13 +127,12 @@ __device__ void norm_solve(InstT &I, const unsigned *zenc, const unsigned *fenc,
     if (lane == 0) *I.degenerate = degen;
 }
 
-// One reference against the point f (normalized objectives): the squared
-// perpendicular distance from the explicit residual r = f - (f . w) w, with
-// w the unit direction j (objective k at wn[k * Hp + j]); keeps the least
-// (strictly less: the least j among equal distances when j ascends).
+// The squared perpendicular distance of the point f (normalized objectives)
+// to the unit direction j (objective k at wn[k * Hp + j]), from the explicit
+// residual r = f - (f . w) w. Every caller forms it with this one sequence of
+// float32 operations, so a recomputed distance has the same bits.
 template <int MO, typename Ptr>
-__device__ __forceinline__ void assoc_ref(const float (&f)[MO], Ptr wn, int Hp, int j,
-                                          float &best, int &bj) {
+__device__ __forceinline__ float assoc_d2(const float (&f)[MO], Ptr wn, int Hp, int j) {
     float w[MO];
 #pragma unroll
     for (int k = 0; k < MO; ++k) w[k] = wn[(size_t)k * Hp + j];
@@ -146,6 +145,15 @@ __device__ __forceinline__ void assoc_ref(const float (&f)[MO], Ptr wn, int Hp, 
         const float r = fmaf(-p, w[k], f[k]);
         d2 = fmaf(r, r, d2);
     }
+    return d2;
+}
+
+// One reference against f; keeps the least distance (strictly less: the
+// least j among equal distances when j ascends).
+template <int MO, typename Ptr>
+__device__ __forceinline__ void assoc_ref(const float (&f)[MO], Ptr wn, int Hp, int j,
+                                          float &best, int &bj) {
+    const float d2 = assoc_d2<MO>(f, wn, Hp, j);
     if (d2 < best) { best = d2; bj = j; }
 }
 
