@@ -19,8 +19,9 @@
 //                    the position-to-point map, per-block tile bounds
 //   k_place_gather   the objective copy in position order (large copies)
 //   k_dominance      triangle of 64x64 tiles: ordered tiles (one direction,
-//                    m - 1 compares per pair), the rest with both directions
-//                    from one set of 2m compares; fused dominator counts
+//                    m - 1 compares per pair, ANDed in EXEC by a v_cmpx
+//                    chain from m = 5), the rest with both directions from
+//                    one set of 2m compares; fused dominator counts
 //   k_dominance_wide the same for m > NARROW_M, objectives in chunks
 //   k_peel           fronts of every instance, persistent over its chunks
 #include <mutex>
@@ -350,16 +351,62 @@ __device__ __forceinline__ void dom_tile(std::integer_sequence<int, Gs...>,
      ...);
 }
 
+// The wave mask of lanes with s_k <= v_k for every k < N (N <= 15), formed
+// in EXEC by a chain of v_cmpx (each compare runs only on the lanes that
+// passed the ones before it), then EXEC is set back to `saved`, the mask the
+// wave entered with. One asm block, so no other vector instruction runs
+// under the narrowed EXEC; unused operand slots repeat slot 0.
+template <int N>
+__device__ __forceinline__ u64 and_le_exec(const float (&s)[15], const float (&v)[15], u64 saved) {
+    static_assert(N >= 1 && N <= 15, "1 to 15 compares");
+    u64 res;
+#define NSGA3_CMPX(i) ".if " #i " < %c[n]\n v_cmpx_le_f32_e32 vcc, %[s" #i "], %[v" #i "]\n.endif\n"
+    asm volatile(NSGA3_CMPX(0) NSGA3_CMPX(1) NSGA3_CMPX(2) NSGA3_CMPX(3) NSGA3_CMPX(4)
+                 NSGA3_CMPX(5) NSGA3_CMPX(6) NSGA3_CMPX(7) NSGA3_CMPX(8) NSGA3_CMPX(9)
+                 NSGA3_CMPX(10) NSGA3_CMPX(11) NSGA3_CMPX(12) NSGA3_CMPX(13) NSGA3_CMPX(14)
+                 "s_mov_b64 %[res], exec\n"
+                 "s_mov_b64 exec, %[save]\n"
+                 : [res] "=s"(res)
+                 : [n] "i"(N), [save] "s"(saved),
+                   [s0] "s"(s[0]), [v0] "v"(v[0]), [s1] "s"(s[1]), [v1] "v"(v[1]),
+                   [s2] "s"(s[2]), [v2] "v"(v[2]), [s3] "s"(s[3]), [v3] "v"(v[3]),
+                   [s4] "s"(s[4]), [v4] "v"(v[4]), [s5] "s"(s[5]), [v5] "v"(v[5]),
+                   [s6] "s"(s[6]), [v6] "v"(v[6]), [s7] "s"(s[7]), [v7] "v"(v[7]),
+                   [s8] "s"(s[8]), [v8] "v"(v[8]), [s9] "s"(s[9]), [v9] "v"(v[9]),
+                   [s10] "s"(s[10]), [v10] "v"(v[10]), [s11] "s"(s[11]), [v11] "v"(v[11]),
+                   [s12] "s"(s[12]), [v12] "v"(v[12]), [s13] "s"(s[13]), [v13] "v"(v[13]),
+                   [s14] "s"(s[14]), [v14] "v"(v[14])
+                 : "vcc");
+#undef NSGA3_CMPX
+    return res;
+}
+
+// From this many objectives the ordered step ANDs its compares in EXEC:
+// m - 1 v_cmpx and two scalar moves per column point, against m - 1 v_cmp
+// and m - 2 s_and (the scalar unit issues at the vector unit's rate, so the
+// s_and chain competes with the compares at large m).
+constexpr int CMPX_MIN_M = 5;
+
 // Ordered tiles: every column point i is in a lower placement bucket than
 // every row point j, so f_1(i) < f_1(j): j cannot dominate i, and
 //   i dominates j  <=>  f_i <= f_j in objectives 2 .. m
 // (m - 1 compares per column point, no reverse word).
 template <int MO, int GW, int R>
 __device__ __forceinline__ void dom_step_ord(const ColV<GW> (&v)[MO], const float (&fj)[MO],
-                                             unsigned &a_lo, unsigned &a_hi) {
+                                             unsigned &a_lo, unsigned &a_hi, u64 exec0) {
     u64 le = ~0ull;
+    if constexpr (MO >= CMPX_MIN_M) {
+        float s[15], w[15];
 #pragma unroll
-    for (int k = 1; k < MO; ++k) le &= ballot(v[k].a[R % GW] <= fj[k]);
+        for (int k = 0; k < 15; ++k) {
+            s[k] = k + 1 < MO ? v[k + 1].a[R % GW] : v[1].a[R % GW];
+            w[k] = k + 1 < MO ? fj[k + 1] : fj[1];
+        }
+        le = and_le_exec<MO - 1>(s, w, exec0);
+    } else {
+#pragma unroll
+        for (int k = 1; k < MO; ++k) le &= ballot(v[k].a[R % GW] <= fj[k]);
+    }
     if (R >= 32) a_hi = shift_in(a_hi, le);
     else a_lo = shift_in(a_lo, le);
     // keep the step's masks short-lived: unconstrained, the scheduler lifts
@@ -388,12 +435,12 @@ template <int MO, int GW, int g, int... Is>
 __device__ __forceinline__ void dom_group_ord(std::integer_sequence<int, Is...>,
                                               const NSGA3_RO float *fi, const float (&fj)[MO],
                                               ColV<GW> (&cur)[MO], ColV<GW> (&nxt)[MO],
-                                              unsigned &a_lo, unsigned &a_hi) {
+                                              unsigned &a_lo, unsigned &a_hi, u64 exec0) {
     __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0)
     __builtin_amdgcn_sched_barrier(0);
     if constexpr (g > 0) load_group_ord<MO, GW, g - 1>(fi, nxt);
     __builtin_amdgcn_sched_barrier(0);
-    (dom_step_ord<MO, GW, GW * g + GW - 1 - Is>(cur, fj, a_lo, a_hi), ...);
+    (dom_step_ord<MO, GW, GW * g + GW - 1 - Is>(cur, fj, a_lo, a_hi, exec0), ...);
 #pragma unroll
     for (int k = 1; k < MO; ++k) cur[k] = nxt[k];
 }
@@ -405,8 +452,9 @@ __device__ __forceinline__ void dom_tile_ord(std::integer_sequence<int, Gs...>,
     constexpr int NG = 64 / GW;
     ColV<GW> cur[MO], nxt[MO];
     load_group_ord<MO, GW, NG - 1>(fi, cur);
+    const u64 exec0 = __builtin_amdgcn_read_exec();
     (dom_group_ord<MO, GW, NG - 1 - Gs>(std::make_integer_sequence<int, GW>{}, fi, fj, cur, nxt,
-                                        a_lo, a_hi),
+                                        a_lo, a_hi, exec0),
      ...);
 }
 
