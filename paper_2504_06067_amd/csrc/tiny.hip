@@ -6,9 +6,9 @@
 // while eleven launches take over sixty.
 //
 // Everything stays in LDS: the objectives, the unit reference directions,
-// each point's dominator bits (the full square of 64 x 64 tiles, half tiles
-// spread over the 16 waves), the fronts, the association keys, the niche counts and the
-// candidate segments. The floating-point steps are the multi-kernel path's
+// each point's dominator bits (the full square of 64 x 64 tiles, quarter
+// tiles spread over the 16 waves), the fronts, the association keys, the
+// niche counts and the candidate segments. The floating-point steps are the multi-kernel path's
 // own (the same ASF operations, the intercept solve of norm_solve, the
 // residual of assoc_ref), so a small instance gives bit-identical results
 // on either path. The niche fill is the same closed form: L* by bisection
@@ -38,15 +38,20 @@ __device__ __forceinline__ void tiny_wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
-// Position of the k-th (0-based) set bit of w.
+// Position of the k-th (0-based) set bit of w (k below the popcount): halves
+// of 32, 16, .. 1 bits, keeping the half that holds it.
 __device__ __forceinline__ int tiny_select_bit(u64 w, int k) {
-    for (int pos = 0; pos < 64; ++pos) {
-        if ((w >> pos) & 1ull) {
-            if (k == 0) return pos;
-            --k;
+    int pos = 0;
+#pragma unroll
+    for (int width = 32; width >= 1; width >>= 1) {
+        const int c = __popcll(w & ((1ull << width) - 1));
+        if (k >= c) {
+            k -= c;
+            w >>= width;
+            pos += width;
         }
     }
-    return -1;
+    return pos;
 }
 
 template <int MO>
@@ -97,6 +102,9 @@ __global__ __launch_bounds__(TINY_THREADS) void k_select_tiny(const Inst I) {
         bad |= isfinite(v) ? 0 : ST_NONFINITE;
         sF[e] = v;
     }
+    // column points past M (to the end of their 64-point block) hold +inf
+    // and dominate nothing
+    for (int e = M * MO + tid; e < W * 64 * MO; e += TINY_THREADS) sF[e] = INFINITY;
     for (int j = tid; j < H; j += TINY_THREADS) {
         // the unit directions of the preparation kernel, operation for operation
         float s = 0.0f;
@@ -122,35 +130,32 @@ __global__ __launch_bounds__(TINY_THREADS) void k_select_tiny(const Inst I) {
         }
     }
 
-    // --- dominance: task (jb, ib, h) takes row block jb (points in the
-    // lanes) against the 32 column points 64 ib + 32 h .. + 31 of block ib,
-    // whose values each lane loads once and hands out by readlane; the tasks
-    // (both halves of every tile of the full square) go round the 16 waves
-    for (int task = wv; task < 2 * W * W; task += TINY_WAVES) {
-        const int jb = task / (2 * W), ib = (task / 2) % W, h = task & 1;
+    // --- dominance: task (jb, ib, q) takes row block jb (points in the
+    // lanes) against the 16 column points 64 ib + 16 q .. + 15 of block ib,
+    // read from LDS at one address per wave (a broadcast); the tasks (the
+    // four quarters of every tile of the full square) go round the 16 waves
+    for (int task = wv; task < 4 * W * W; task += TINY_WAVES) {
+        const int jb = task / (4 * W), ib = (task / 4) % W, q = task & 3;
         const int j = jb * 64 + lane;
-        const int ci = ib * 64 + 32 * h + (lane & 31);  // column point of lane (and lane + 32)
-        float fj[MO], fc[MO];
+        const int c0 = uniform(ib * 64 + 16 * q);
+        float fj[MO];
 #pragma unroll
-        for (int k = 0; k < MO; ++k) {
-            fj[k] = j < M ? sF[j * MO + k] : INFINITY;
-            fc[k] = ci < M ? sF[ci * MO + k] : INFINITY;
-        }
-        // R runs 31 down to 0, so the shifted-in bit of column point R lands
-        // at bit R; column points past M hold +inf and dominate nothing
-        unsigned A = 0;  // bit R: point 64 ib + 32 h + R dominates j
+        for (int k = 0; k < MO; ++k) fj[k] = j < M ? sF[j * MO + k] : INFINITY;
+        // R runs 15 down to 0, so the shifted-in bit of column point c0 + R
+        // lands at bit R
+        unsigned A = 0;  // bit R: point c0 + R dominates j
 #pragma unroll 4
-        for (int R = 31; R >= 0; --R) {
+        for (int R = 15; R >= 0; --R) {
             u64 lt = 0, gt = 0;
 #pragma unroll
             for (int k = 0; k < MO; ++k) {
-                const float x = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(fc[k]), R));
+                const float x = sF[(c0 + R) * MO + k];
                 lt |= ballot(x < fj[k]);
                 gt |= ballot(x > fj[k]);
             }
             A = shift_in(A, lt & ~gt);
         }
-        if (j < M) ((unsigned *)sDom)[(j * TINY_W + ib) * 2 + h] = A;  // low half: h = 0
+        if (j < M) ((unsigned short *)sDom)[(j * TINY_W + ib) * 4 + q] = (unsigned short)A;
     }
     lds_barrier();
     // --- fronts: point x = tid (waves 0 .. W-1); front k = alive points
