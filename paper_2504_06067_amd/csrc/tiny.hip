@@ -357,6 +357,12 @@ __global__ __launch_bounds__(TINY_THREADS) void k_select_tiny(const Inst I) {
         }
     }
     lds_barrier();  // offsets and picks per reference are complete
+    // the rank among the remaining candidates of every keyed pick, computed
+    // up front in parallel (the association keys are no longer needed):
+    // pick i of reference j, at level rho_j + i, is stored at sOff[j] + i;
+    // each member's distance is copied to its segment slot
+    int *sPickRank = (int *)sKey;
+    float *sSegD = (float *)sKey + TINY_M;
     if (own && myrank == l) {
         // slot: last-front members of the same reference with a smaller index
         const int p = sPi[tid];
@@ -364,8 +370,14 @@ __global__ __launch_bounds__(TINY_THREADS) void k_select_tiny(const Inst I) {
 #pragma unroll 8
         for (int y = 0; y < tid; ++y) slot += sPl[y] == p;
         sMemb[sOff[p] + slot] = tid;
+        sSegD[sOff[p] + slot] = sD[tid];
+        const int rh = sRho[p];
+        if (slot < sTp[p] && rh + slot > 0)
+            sPickRank[sOff[p] + slot] =
+                (int)(tie_key(seed, 2u, (unsigned)p, (unsigned)(rh + slot)) %
+                      (u64)(sCnt[p] - slot));
     }
-    lds_barrier();  // the segments are complete
+    lds_barrier();  // the segments and pick ranks are complete
     for (int j = tid; j < H; j += TINY_THREADS) {
         const int t = sTp[j], c = sCnt[j], rh = sRho[j];
         if (t <= 0) continue;
@@ -385,14 +397,14 @@ __global__ __launch_bounds__(TINY_THREADS) void k_select_tiny(const Inst I) {
             if (lev == 0) {
                 // the nearest candidate (least distance, then least index)
                 u64 best = ~0ull;
+                const float *segd = sSegD + sOff[j];
                 for (int i = 0; i < c; ++i) {
-                    const u64 k = ((u64)__float_as_uint(sD[seg[i]]) << 32) | (unsigned)i;
+                    const u64 k = ((u64)__float_as_uint(segd[i]) << 32) | (unsigned)i;
                     best = k < best ? k : best;
                 }
                 pos = (int)(unsigned)(best & 0xffffffffull);
             } else {
-                int kk = (int)(tie_key(seed, 2u, (unsigned)j, (unsigned)lev) %
-                               (u64)(c - (lev - rh)));
+                int kk = sPickRank[sOff[j] + (lev - rh)];
 #pragma unroll
                 for (int w = 0; w < TINY_W; ++w) {
                     const int pc = __popcll(rem[w]);
