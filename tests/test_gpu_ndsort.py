@@ -31,6 +31,27 @@ def test_ranks_exact(kind, M, m):
     assert np.array_equal(fi, ref_fi)
 
 
+@pytest.mark.parametrize("kind", ["continuous", "grid", "signed_zero"])
+@pytest.mark.parametrize("m", list(range(5, 17)))
+def test_ordered_tiles_every_m(kind, m):
+    """Every compare count of the ordered tiles' EXEC-chained compares (m - 1
+    of them, m = 5 .. 16): 777 points (13 blocks, a ragged last one), most
+    tiles ordered by the first-objective placement; ties on a grid, and
+    -0.0 against +0.0 in every objective."""
+    dev = device()
+    rng = np.random.default_rng(1000 + m)
+    if kind == "continuous":
+        F = rng.random((777, m)).astype(np.float32)
+    else:
+        F = rng.integers(0, 4, (777, m)).astype(np.float32)
+        if kind == "signed_zero":
+            F[(F == 0) & (rng.random(F.shape) < 0.5)] = np.float32(-0.0)
+    ref_rank, ref_fi = oracle.nd_sort(F, 0)
+    rank, fi = run(F, 0, dev)
+    assert np.array_equal(rank, ref_rank)
+    assert np.array_equal(fi, ref_fi)
+
+
 @pytest.mark.parametrize("n_stop", [1, 7, 100, 500, 999, 1000])
 def test_early_stop(n_stop):
     dev = device()
