@@ -354,16 +354,21 @@ __device__ __forceinline__ void dom_tile(std::integer_sequence<int, Gs...>,
 // The wave mask of lanes with s_k <= v_k for every k < N (N <= 15), formed
 // in EXEC by a chain of v_cmpx (each compare runs only on the lanes that
 // passed the ones before it), then EXEC is set back to `saved`, the mask the
-// wave entered with. One asm block, so no other vector instruction runs
-// under the narrowed EXEC; unused operand slots repeat slot 0.
+// wave entered with. From N = 6 on, a wave with no lane left after four
+// compares skips the rest (the mask is then empty either way). One asm
+// block, so no other vector instruction runs under the narrowed EXEC;
+// unused operand slots repeat slot 0.
 template <int N>
 __device__ __forceinline__ u64 and_le_exec(const float (&s)[15], const float (&v)[15], u64 saved) {
     static_assert(N >= 1 && N <= 15, "1 to 15 compares");
     u64 res;
 #define NSGA3_CMPX(i) ".if " #i " < %c[n]\n v_cmpx_le_f32_e32 vcc, %[s" #i "], %[v" #i "]\n.endif\n"
-    asm volatile(NSGA3_CMPX(0) NSGA3_CMPX(1) NSGA3_CMPX(2) NSGA3_CMPX(3) NSGA3_CMPX(4)
-                 NSGA3_CMPX(5) NSGA3_CMPX(6) NSGA3_CMPX(7) NSGA3_CMPX(8) NSGA3_CMPX(9)
+    asm volatile(NSGA3_CMPX(0) NSGA3_CMPX(1) NSGA3_CMPX(2) NSGA3_CMPX(3)
+                 ".if 5 < %c[n]\n s_cbranch_execz 1f\n.endif\n"
+                 NSGA3_CMPX(4) NSGA3_CMPX(5) NSGA3_CMPX(6)
+                 NSGA3_CMPX(7) NSGA3_CMPX(8) NSGA3_CMPX(9)
                  NSGA3_CMPX(10) NSGA3_CMPX(11) NSGA3_CMPX(12) NSGA3_CMPX(13) NSGA3_CMPX(14)
+                 "1:\n"
                  "s_mov_b64 %[res], exec\n"
                  "s_mov_b64 exec, %[save]\n"
                  : [res] "=s"(res)
