@@ -151,12 +151,14 @@ constexpr long long ASSOC_WAVES = 16384;
 // DOM_MAX_TILES tiles per item: measured on one MI355X, a single round of
 // long items loses 10-25 % to uneven wave placement, and items of 2-3 tiles
 // amortize the per-item setup (one tile per item costs up to 8 % on small
-// triangles). Launches of millions of tiles take longer items: the waves
+// triangles; two rounds give the large workload's 49 k tiles 3 tiles per
+// item, 35.5 us against 36.0 us with three rounds of 2-tile items).
+// Launches of millions of tiles take longer items: the waves
 // of 3-tile items averaged 3.9 resident per SIMD of 7 (per-wave setup and
 // the refill of finished workgroups), and 12 tiles per item cut the
 // many-objective launch (2.1 M tiles) from 3.55 to 3.40 ms; 96 are slower.
 constexpr long long DOM_WAVES_PER_CU = 32;
-constexpr long long DOM_ROUNDS = 3;
+constexpr long long DOM_ROUNDS = 2;
 constexpr long long DOM_MAX_TILES = 12;
 
 static int auto_slice(int H, long long sum_W, int m) {
