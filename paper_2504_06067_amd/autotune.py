@@ -25,7 +25,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 TABLE_PATH = os.path.join(_HERE, "tiles.json")
 
 R_CANDIDATES = (32, 64, 128, 256, 512)
-G_CANDIDATES = (1, 2, 3, 4, 6)
+G_CANDIDATES = (1, 2, 3, 4, 6, 12)
 G_MARGIN = 0.02
 
 _table = None
