@@ -21,7 +21,8 @@
 //   k_dominance      triangle of 64x64 tiles: ordered tiles (one direction,
 //                    m - 1 compares per pair, ANDed in EXEC by a v_cmpx
 //                    chain from m = 5), the rest with both directions from
-//                    one set of 2m compares; fused dominator counts
+//                    one set of 2m compares (two v_cmpx chains from m = 5);
+//                    fused dominator counts
 //   k_dominance_wide the same for m > NARROW_M, objectives in chunks
 //   k_peel           fronts of every instance, persistent over its chunks
 #include <mutex>
@@ -296,25 +297,125 @@ struct alignas(4 * GW) ColV {
     float a[GW];
 };
 
+// The wave mask of lanes with s_k <= v_k for every k < N (N <= 15), formed
+// in EXEC by a chain of v_cmpx (each compare runs only on the lanes that
+// passed the ones before it), then EXEC is set back to `saved`, the mask the
+// wave entered with. From N = 6 on, a wave with no lane left after four
+// compares skips the rest (the mask is then empty either way). One asm
+// block, so no other vector instruction runs under the narrowed EXEC;
+// unused operand slots repeat slot 0.
+template <int N>
+__device__ __forceinline__ u64 and_le_exec(const float (&s)[15], const float (&v)[15], u64 saved) {
+    static_assert(N >= 1 && N <= 15, "1 to 15 compares");
+    u64 res;
+#define NSGA3_CMPX(i) ".if " #i " < %c[n]\n v_cmpx_le_f32_e32 vcc, %[s" #i "], %[v" #i "]\n.endif\n"
+    asm volatile(NSGA3_CMPX(0) NSGA3_CMPX(1) NSGA3_CMPX(2) NSGA3_CMPX(3)
+                 ".if 5 < %c[n]\n s_cbranch_execz 1f\n.endif\n"
+                 NSGA3_CMPX(4) NSGA3_CMPX(5) NSGA3_CMPX(6)
+                 NSGA3_CMPX(7) NSGA3_CMPX(8) NSGA3_CMPX(9)
+                 NSGA3_CMPX(10) NSGA3_CMPX(11) NSGA3_CMPX(12) NSGA3_CMPX(13) NSGA3_CMPX(14)
+                 "1:\n"
+                 "s_mov_b64 %[res], exec\n"
+                 "s_mov_b64 exec, %[save]\n"
+                 : [res] "=s"(res)
+                 : [n] "i"(N), [save] "s"(saved),
+                   [s0] "s"(s[0]), [v0] "v"(v[0]), [s1] "s"(s[1]), [v1] "v"(v[1]),
+                   [s2] "s"(s[2]), [v2] "v"(v[2]), [s3] "s"(s[3]), [v3] "v"(v[3]),
+                   [s4] "s"(s[4]), [v4] "v"(v[4]), [s5] "s"(s[5]), [v5] "v"(v[5]),
+                   [s6] "s"(s[6]), [v6] "v"(v[6]), [s7] "s"(s[7]), [v7] "v"(v[7]),
+                   [s8] "s"(s[8]), [v8] "v"(v[8]), [s9] "s"(s[9]), [v9] "v"(v[9]),
+                   [s10] "s"(s[10]), [v10] "v"(v[10]), [s11] "s"(s[11]), [v11] "v"(v[11]),
+                   [s12] "s"(s[12]), [v12] "v"(v[12]), [s13] "s"(s[13]), [v13] "v"(v[13]),
+                   [s14] "s"(s[14]), [v14] "v"(v[14])
+                 : "vcc");
+#undef NSGA3_CMPX
+    return res;
+}
+
+// As and_le_exec, with s_k >= v_k.
+template <int N>
+__device__ __forceinline__ u64 and_ge_exec(const float (&s)[15], const float (&v)[15], u64 saved) {
+    static_assert(N >= 1 && N <= 15, "1 to 15 compares");
+    u64 res;
+#define NSGA3_CMPXG(i) ".if " #i " < %c[n]\n v_cmpx_ge_f32_e32 vcc, %[s" #i "], %[v" #i "]\n.endif\n"
+    asm volatile(NSGA3_CMPXG(0) NSGA3_CMPXG(1) NSGA3_CMPXG(2) NSGA3_CMPXG(3)
+                 ".if 5 < %c[n]\n s_cbranch_execz 1f\n.endif\n"
+                 NSGA3_CMPXG(4) NSGA3_CMPXG(5) NSGA3_CMPXG(6)
+                 NSGA3_CMPXG(7) NSGA3_CMPXG(8) NSGA3_CMPXG(9)
+                 NSGA3_CMPXG(10) NSGA3_CMPXG(11) NSGA3_CMPXG(12) NSGA3_CMPXG(13) NSGA3_CMPXG(14)
+                 "1:\n"
+                 "s_mov_b64 %[res], exec\n"
+                 "s_mov_b64 exec, %[save]\n"
+                 : [res] "=s"(res)
+                 : [n] "i"(N), [save] "s"(saved),
+                   [s0] "s"(s[0]), [v0] "v"(v[0]), [s1] "s"(s[1]), [v1] "v"(v[1]),
+                   [s2] "s"(s[2]), [v2] "v"(v[2]), [s3] "s"(s[3]), [v3] "v"(v[3]),
+                   [s4] "s"(s[4]), [v4] "v"(v[4]), [s5] "s"(s[5]), [v5] "v"(v[5]),
+                   [s6] "s"(s[6]), [v6] "v"(v[6]), [s7] "s"(s[7]), [v7] "v"(v[7]),
+                   [s8] "s"(s[8]), [v8] "v"(v[8]), [s9] "s"(s[9]), [v9] "v"(v[9]),
+                   [s10] "s"(s[10]), [v10] "v"(v[10]), [s11] "s"(s[11]), [v11] "v"(v[11]),
+                   [s12] "s"(s[12]), [v12] "v"(v[12]), [s13] "s"(s[13]), [v13] "v"(v[13]),
+                   [s14] "s"(s[14]), [v14] "v"(v[14])
+                 : "vcc");
+#undef NSGA3_CMPXG
+    return res;
+}
+
+// From this many objectives the ordered step ANDs its compares in EXEC:
+// m - 1 v_cmpx and two scalar moves per column point, against m - 1 v_cmp
+// and m - 2 s_and (the scalar unit issues at the vector unit's rate, so the
+// s_and chain competes with the compares at large m).
+constexpr int CMPX_MIN_M = 5;
+
 // One compare step against column point i = 64 * ib + R (uniform, objective
 // values v[k].a[R % GW]): the wave masks lt = {j : f_i < f_j in some
 // objective}, gt = {j : f_i > f_j in some objective} come from 2m compares;
 // then
 //   i dominates j  <=>  j in lt \ gt   (bit R of lane j's word A)
 //   j dominates i  <=>  j in gt \ lt   (the whole mask is row i's word B)
+// From CMPX_MIN_M objectives the compares form two EXEC chains instead, le =
+// {j : f_i <= f_j in every objective} and ge = {j : f_i >= f_j in every
+// objective}, with lt \ gt = le \ ge and gt \ lt = ge \ le.
 template <int MO, int GW, int R>
 __device__ __forceinline__ void dom_step(const ColV<GW> (&v)[MO], const float (&fj)[MO],
                                          unsigned &a_lo, unsigned &a_hi, unsigned &b_lo,
                                          unsigned &b_hi) {
-    u64 lt = 0, gt = 0;
+    u64 i_dom_j, j_dom_i;
+    if constexpr (MO >= CMPX_MIN_M && MO <= 16) {
+        // all <= (le) and all >= (ge) by EXEC chains: i dominates j when le
+        // and not ge (some objective strictly less), j dominates i when ge
+        // and not le
+        float s[15], w[15];
+        const u64 e0 = __builtin_amdgcn_read_exec();
+        u64 le = ~0ull, ge = ~0ull;
+        {
 #pragma unroll
-    for (int k = 0; k < MO; ++k) {
-        const float x = v[k].a[R % GW];
-        lt |= ballot(x < fj[k]);
-        gt |= ballot(x > fj[k]);
+            for (int k = 0; k < 15; ++k) {
+                s[k] = k < MO ? v[k].a[R % GW] : v[0].a[R % GW];
+                w[k] = k < MO ? fj[k] : fj[0];
+            }
+        }
+        if constexpr (MO <= 15) {
+            le = and_le_exec<MO>(s, w, e0);
+            ge = and_ge_exec<MO>(s, w, e0);
+        } else {
+            // the 16th objective by a plain compare
+            le = and_le_exec<15>(s, w, e0) & ballot(v[15].a[R % GW] <= fj[15]);
+            ge = and_ge_exec<15>(s, w, e0) & ballot(v[15].a[R % GW] >= fj[15]);
+        }
+        i_dom_j = le & ~ge;
+        j_dom_i = ge & ~le;
+    } else {
+        u64 lt = 0, gt = 0;
+#pragma unroll
+        for (int k = 0; k < MO; ++k) {
+            const float x = v[k].a[R % GW];
+            lt |= ballot(x < fj[k]);
+            gt |= ballot(x > fj[k]);
+        }
+        i_dom_j = lt & ~gt;
+        j_dom_i = gt & ~lt;
     }
-    const u64 i_dom_j = lt & ~gt;
-    const u64 j_dom_i = gt & ~lt;
     if (R >= 32) a_hi = shift_in(a_hi, i_dom_j);
     else a_lo = shift_in(a_lo, i_dom_j);
     b_lo = write_lane<R>(b_lo, (unsigned)j_dom_i);
@@ -351,46 +452,6 @@ __device__ __forceinline__ void dom_tile(std::integer_sequence<int, Gs...>,
      ...);
 }
 
-// The wave mask of lanes with s_k <= v_k for every k < N (N <= 15), formed
-// in EXEC by a chain of v_cmpx (each compare runs only on the lanes that
-// passed the ones before it), then EXEC is set back to `saved`, the mask the
-// wave entered with. From N = 6 on, a wave with no lane left after four
-// compares skips the rest (the mask is then empty either way). One asm
-// block, so no other vector instruction runs under the narrowed EXEC;
-// unused operand slots repeat slot 0.
-template <int N>
-__device__ __forceinline__ u64 and_le_exec(const float (&s)[15], const float (&v)[15], u64 saved) {
-    static_assert(N >= 1 && N <= 15, "1 to 15 compares");
-    u64 res;
-#define NSGA3_CMPX(i) ".if " #i " < %c[n]\n v_cmpx_le_f32_e32 vcc, %[s" #i "], %[v" #i "]\n.endif\n"
-    asm volatile(NSGA3_CMPX(0) NSGA3_CMPX(1) NSGA3_CMPX(2) NSGA3_CMPX(3)
-                 ".if 5 < %c[n]\n s_cbranch_execz 1f\n.endif\n"
-                 NSGA3_CMPX(4) NSGA3_CMPX(5) NSGA3_CMPX(6)
-                 NSGA3_CMPX(7) NSGA3_CMPX(8) NSGA3_CMPX(9)
-                 NSGA3_CMPX(10) NSGA3_CMPX(11) NSGA3_CMPX(12) NSGA3_CMPX(13) NSGA3_CMPX(14)
-                 "1:\n"
-                 "s_mov_b64 %[res], exec\n"
-                 "s_mov_b64 exec, %[save]\n"
-                 : [res] "=s"(res)
-                 : [n] "i"(N), [save] "s"(saved),
-                   [s0] "s"(s[0]), [v0] "v"(v[0]), [s1] "s"(s[1]), [v1] "v"(v[1]),
-                   [s2] "s"(s[2]), [v2] "v"(v[2]), [s3] "s"(s[3]), [v3] "v"(v[3]),
-                   [s4] "s"(s[4]), [v4] "v"(v[4]), [s5] "s"(s[5]), [v5] "v"(v[5]),
-                   [s6] "s"(s[6]), [v6] "v"(v[6]), [s7] "s"(s[7]), [v7] "v"(v[7]),
-                   [s8] "s"(s[8]), [v8] "v"(v[8]), [s9] "s"(s[9]), [v9] "v"(v[9]),
-                   [s10] "s"(s[10]), [v10] "v"(v[10]), [s11] "s"(s[11]), [v11] "v"(v[11]),
-                   [s12] "s"(s[12]), [v12] "v"(v[12]), [s13] "s"(s[13]), [v13] "v"(v[13]),
-                   [s14] "s"(s[14]), [v14] "v"(v[14])
-                 : "vcc");
-#undef NSGA3_CMPX
-    return res;
-}
-
-// From this many objectives the ordered step ANDs its compares in EXEC:
-// m - 1 v_cmpx and two scalar moves per column point, against m - 1 v_cmp
-// and m - 2 s_and (the scalar unit issues at the vector unit's rate, so the
-// s_and chain competes with the compares at large m).
-constexpr int CMPX_MIN_M = 5;
 
 // Ordered tiles: every column point i is in a lower placement bucket than
 // every row point j, so f_1(i) < f_1(j): j cannot dominate i, and
